@@ -1,0 +1,229 @@
+"""FP64 CPU oracle of the two-fluid finite-volume update (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  The product library never loads it
+and the two share no code: this wrapper and ``oracle.c`` implement the update
+independently from the paper (Eq. (1), Sec. 2.1-2.2; scheme of Sec. 3).
+
+The compiled library ``_oracle.so`` is built by :func:`build` with gcc,
+``-O2 -ffp-contract=off`` (no fused multiply-add, no fast-math) and OpenMP over
+independent rows/columns.
+
+Parity status of each function is recorded in the design notes: every entry
+point here is pinned by the ``-m "not gpu"`` tests against closed forms, the
+exact Riemann solution, Rankine-Hugoniot jumps, conservation and symmetry.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "_oracle.so")
+
+TRANSMISSIVE = 0
+PERIODIC = 1
+VANLEER = 0
+MINMOD = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into _oracle.so (gcc, FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("bc_xlo", C.c_int32), ("bc_xhi", C.c_int32), ("bc_ylo", C.c_int32),
+                ("bc_yhi", C.c_int32), ("gamma1", C.c_double), ("pinf1", C.c_double),
+                ("gamma2", C.c_double), ("pinf2", C.c_double), ("cfl", C.c_double),
+                ("zeps", C.c_double), ("limiter", C.c_int32), ("pad_", C.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.POINTER(_Problem)
+        D = C.POINTER(C.c_double)
+        I64 = C.POINTER(C.c_int64)
+        lib.or_prim_to_cons.argtypes = [P, D, D]
+        lib.or_cons_to_prim.argtypes = [P, D, D]
+        lib.or_max_speed.argtypes = [P, D]
+        lib.or_max_speed.restype = C.c_double
+        lib.or_step.argtypes = [P, D, D, C.c_int64, C.c_double]
+        lib.or_dt.argtypes = [P, D, C.c_double, C.c_double, D, D]
+        lib.or_dt.restype = C.c_int
+        lib.or_run.argtypes = [P, D, C.c_int64, C.c_int64, D, C.c_double, D]
+        lib.or_run.restype = C.c_int64
+        lib.or_step_cells.argtypes = [P, D, C.c_int64, C.c_double, I64, C.c_int64, D]
+        lib.or_unit_cons_to_prim.argtypes = [P, D, D, D, D]
+        lib.or_unit_limiter.argtypes = [C.c_double, C.c_double, C.c_int32]
+        lib.or_unit_limiter.restype = C.c_double
+        lib.or_unit_face_states.argtypes = [D, D, D, C.c_double, C.c_double, C.c_double,
+                                            C.c_int32, D, D]
+        lib.or_unit_hllc.argtypes = [P, D, D, D]
+        lib.or_unit_sweep_line.argtypes = [P, C.c_int64, D, D, C.c_double]
+        lib.or_num_threads.restype = C.c_int32
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+@dataclass
+class Problem:
+    """Grid, boundaries, materials and scheme options of one solve.
+
+    Phase 1 is the gas (air, ideal gas: pinf1 = 0), phase 2 the liquid.
+    """
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    gamma1: float = 1.4
+    pinf1: float = 0.0
+    gamma2: float = 4.4
+    pinf2: float = 6.0e8
+    cfl: float = 0.4
+    zeps: float = 1.0e-6
+    limiter: int = VANLEER
+    bc_xlo: int = TRANSMISSIVE
+    bc_xhi: int = TRANSMISSIVE
+    bc_ylo: int = TRANSMISSIVE
+    bc_yhi: int = TRANSMISSIVE
+
+    def _c(self) -> _Problem:
+        return _Problem(self.nx, self.ny, self.dx, self.dy, self.bc_xlo, self.bc_xhi,
+                        self.bc_ylo, self.bc_yhi, self.gamma1, self.pinf1, self.gamma2,
+                        self.pinf2, self.cfl, self.zeps, self.limiter, 0)
+
+
+class Oracle:
+    """Stateful FP64 solve on the CPU: U holds the 6 conserved planes."""
+
+    def __init__(self, prob: Problem):
+        self.prob = prob
+        self._p = prob._c()
+        self.U = np.zeros((6, prob.ny, prob.nx), dtype=np.float64)
+        self.t = 0.0
+        self.step = 0
+        self.last_dt = 0.0
+
+    # -- state -------------------------------------------------------------
+    def set_primitive(self, prim: np.ndarray) -> None:
+        """prim: (6, ny, nx) planes z1, rho1, rho2, u, v, p."""
+        prim = np.ascontiguousarray(prim, dtype=np.float64)
+        assert prim.shape == self.U.shape
+        _load().or_prim_to_cons(C.byref(self._p), _dp(prim), _dp(self.U))
+
+    def set_conserved(self, U: np.ndarray) -> None:
+        self.U[...] = U
+
+    def primitive(self) -> dict:
+        out = np.empty((6, self.prob.ny, self.prob.nx), dtype=np.float64)
+        _load().or_cons_to_prim(C.byref(self._p), _dp(self.U), _dp(out))
+        return dict(rho=out[0], u=out[1], v=out[2], p=out[3], c=out[4], z1=out[5])
+
+    # -- time stepping -----------------------------------------------------
+    def max_speed(self) -> float:
+        return _load().or_max_speed(C.byref(self._p), _dp(self.U))
+
+    def cfl_dt(self, t_end: float = 0.0):
+        dt = C.c_double()
+        tn = C.c_double()
+        rc = _load().or_dt(C.byref(self._p), _dp(self.U), self.t, t_end, C.byref(dt),
+                           C.byref(tn))
+        if rc != 0:
+            raise FloatingPointError("non-finite state or no positive signal speed")
+        return dt.value, tn.value
+
+    def step_dt(self, dt: float) -> None:
+        """One step with a given dt."""
+        tmp = np.empty_like(self.U)
+        _load().or_step(C.byref(self._p), _dp(self.U), _dp(tmp), self.step, dt)
+        self.step += 1
+        self.t += dt
+        self.last_dt = dt
+
+    def run(self, nsteps: int, t_end: float = 0.0) -> int:
+        t = C.c_double(self.t)
+        ldt = C.c_double(self.last_dt)
+        n = _load().or_run(C.byref(self._p), _dp(self.U), self.step, nsteps, C.byref(t),
+                           t_end, C.byref(ldt))
+        if n < 0:
+            raise FloatingPointError("oracle: non-finite state")
+        self.step += n
+        self.t = t.value
+        self.last_dt = ldt.value
+        return int(n)
+
+    def step_cells(self, U: np.ndarray, step: int, dt: float, cells: np.ndarray) -> np.ndarray:
+        """Post-step state at flat cell indices j*nx+i, from pre-step state U."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty((6, cells.size), dtype=np.float64)
+        _load().or_step_cells(C.byref(self._p), _dp(U), step, dt,
+                              cells.ctypes.data_as(C.POINTER(C.c_int64)), cells.size, _dp(out))
+        return out
+
+
+# -- building blocks for unit pins -----------------------------------------
+def unit_cons_to_prim(prob: Problem, q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    w = np.empty(6)
+    r = C.c_double()
+    rc2 = C.c_double()
+    _load().or_unit_cons_to_prim(C.byref(prob._c()), _dp(q), _dp(w), C.byref(r), C.byref(rc2))
+    return w, r.value, rc2.value
+
+
+def unit_limiter(a: float, b: float, limiter: int) -> float:
+    return _load().or_unit_limiter(a, b, limiter)
+
+
+def unit_face_states(wm, w0, wp, r, rc2, hl, limiter):
+    wm, w0, wp = (np.ascontiguousarray(x, dtype=np.float64) for x in (wm, w0, wp))
+    wl = np.empty(6)
+    wh = np.empty(6)
+    _load().or_unit_face_states(_dp(wm), _dp(w0), _dp(wp), r, rc2, hl, limiter, _dp(wl),
+                                _dp(wh))
+    return wl, wh
+
+
+def unit_hllc(prob: Problem, wL, wR) -> np.ndarray:
+    wL = np.ascontiguousarray(wL, dtype=np.float64)
+    wR = np.ascontiguousarray(wR, dtype=np.float64)
+    out = np.empty(7)
+    _load().or_unit_hllc(C.byref(prob._c()), _dp(wL), _dp(wR), _dp(out))
+    return out
+
+
+def unit_sweep_line(prob: Problem, q: np.ndarray, lam: float) -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.empty_like(q)
+    _load().or_unit_sweep_line(C.byref(prob._c()), q.shape[1], _dp(q), _dp(out), lam)
+    return out
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())

@@ -1,0 +1,296 @@
+"""Seeded synthetic inputs: shock / air-bubble scenarios in water.
+
+This module only builds primitive fields (volume fraction, phase densities,
+velocity, pressure) on a cell-centred grid.  It holds none of the solver's
+arithmetic: the conversion to conserved variables is done separately by the
+solver library and by the test oracle.  Both take these fields as plain data.
+
+Scenario shapes follow the problem statement of the paper (Sec. 2.4): a planar
+shocked region at the left end feeding a right-running shock into a liquid
+seeded with air-filled cavities, transverse periodic or transmissive walls.
+The energetic liquid of the paper is replaced by inert water (stiffened gas,
+gamma = 4.4, p_inf = 6e8 Pa); air is an ideal gas (gamma = 1.4, Table 2).
+
+Interfaces are smeared with a tanh profile one cell wide; the air volume
+fraction is z1 = eps + (1 - 2 eps) w with w in [0, 1] the smeared indicator.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+WATER_GAMMA = 4.4
+WATER_PINF = 6.0e8
+AIR_GAMMA = 1.4          # Table 2
+AIR_PINF = 0.0
+P_AMBIENT = 1.0e5        # Sec. 2.4: initial pressure of unshocked materials
+RHO_AIR = 1.2            # Sec. 2.4: initial air density
+RHO_WATER = 1000.0
+Z_EPS = 1.0e-6
+
+SEEDS = {"random_4096x2048": 1905, "roofline_8192": 5727, "serving": 2019}
+
+
+@dataclass
+class Scenario:
+    """Primitive initial fields plus the grid / material description."""
+    name: str
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    prim: np.ndarray                      # (6, ny, nx): z1, rho1, rho2, u, v, p
+    cfl: float = 0.4
+    limiter: str = "vanleer"
+    bc: tuple = ("transmissive",) * 4     # xlo, xhi, ylo, yhi
+    gamma1: float = AIR_GAMMA
+    pinf1: float = AIR_PINF
+    gamma2: float = WATER_GAMMA
+    pinf2: float = WATER_PINF
+    zeps: float = Z_EPS
+    steps: int = 0                        # step count of the workload
+    t_end: float = 0.0                    # end time of the workload (0: none)
+    meta: dict = field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------
+# Rankine-Hugoniot state behind a planar shock in a stiffened gas
+# (the shocked inflow region of Sec. 2.4, here for water instead of NM).
+def stiffened_gas_shock(p1: float, rho0: float = RHO_WATER, p0: float = P_AMBIENT,
+                        gamma: float = WATER_GAMMA, pinf: float = WATER_PINF):
+    """State behind a right-running shock of pressure p1 into gas at rest.
+
+    A stiffened gas behaves as an ideal gas in the shifted pressure p + p_inf,
+    so the ideal-gas Hugoniot applies with p -> p + p_inf.
+    Returns (rho1, u1, shock_speed).
+    """
+    P0 = p0 + pinf
+    P1 = p1 + pinf
+    mu = (gamma - 1.0) / (gamma + 1.0)
+    ratio = P1 / P0
+    rho1 = rho0 * (ratio + mu) / (mu * ratio + 1.0)
+    c0 = math.sqrt(gamma * P0 / rho0)
+    S = c0 * math.sqrt((gamma + 1.0) / (2.0 * gamma) * ratio + (gamma - 1.0) / (2.0 * gamma))
+    u1 = S * (1.0 - rho0 / rho1)
+    return rho1, u1, S
+
+
+# --------------------------------------------------------------------------
+# Cavity-field arithmetic printed in the paper (used by the paper-shaped
+# scenario helpers and pinned against its worked numbers).
+def regular_spacing(d_c: float, phi: float) -> float:
+    """Eq. (6_1): spacing of a square cavity array of porosity phi."""
+    return math.sqrt(math.pi * d_c * d_c / (4.0 * phi))
+
+
+def cavity_count(phi: float, L: float, W: float, d_c: float) -> float:
+    """Eq. (7): number of equal cavities of diameter d_c in an L x W domain."""
+    return 4.0 * phi * L * W / (math.pi * d_c * d_c)
+
+
+def number_density_3d(phi: float, d_c: float) -> float:
+    """Sec. 5.5: equivalent 3-D number density 6 phi / (pi d_c^3)."""
+    return 6.0 * phi / (math.pi * d_c ** 3)
+
+
+# --------------------------------------------------------------------------
+def _zfrac(w: np.ndarray, eps: float) -> np.ndarray:
+    return eps + (1.0 - 2.0 * eps) * w
+
+
+def _blank(nx: int, ny: int) -> np.ndarray:
+    prim = np.empty((6, ny, nx), dtype=np.float64)
+    prim[0] = 0.0            # w (air indicator), turned into z1 at the end
+    prim[1] = RHO_AIR
+    prim[2] = RHO_WATER
+    prim[3] = 0.0
+    prim[4] = 0.0
+    prim[5] = P_AMBIENT
+    return prim
+
+
+def _paint_bubble(w: np.ndarray, xc: float, yc: float, R: float) -> None:
+    """w = max(w, 0.5 (1 - tanh(r - R))) with r in cell units, cell centres at
+    (i + 0.5, j + 0.5); evaluated on a window wide enough for the tail to
+    fall below 1e-13."""
+    ny, nx = w.shape
+    h = R + 16.0
+    i0 = max(0, int(math.floor(xc - h)))
+    i1 = min(nx, int(math.ceil(xc + h)) + 1)
+    j0 = max(0, int(math.floor(yc - h)))
+    j1 = min(ny, int(math.ceil(yc + h)) + 1)
+    if i0 >= i1 or j0 >= j1:
+        return
+    xs = (np.arange(i0, i1, dtype=np.float64) + 0.5) - xc
+    ys = (np.arange(j0, j1, dtype=np.float64) + 0.5) - yc
+    r = np.sqrt(ys[:, None] * ys[:, None] + xs[None, :] * xs[None, :])
+    wb = 0.5 * (1.0 - np.tanh(r - R))
+    np.maximum(w[j0:j1, i0:i1], wb, out=w[j0:j1, i0:i1])
+
+
+def _finish(prim: np.ndarray, eps: float) -> np.ndarray:
+    prim[0] = _zfrac(prim[0], eps)
+    return prim
+
+
+def place_bubbles(rng: np.random.Generator, n: int, nx: int, ny: int, rmin: float,
+                  rmax: float, gap: float, x_lo: float, max_draws: int = 1_000_000):
+    """Seeded rejection sampling of n non-overlapping circles (cell units).
+
+    Radius uniform in [rmin, rmax]; centre uniform with the circle inside
+    [x_lo + gap, nx - gap] x [gap, ny - gap]; edge-to-edge distance to every
+    accepted circle at least `gap`.  Raises after max_draws rejected draws.
+    """
+    xs = np.empty(n)
+    ys = np.empty(n)
+    rs = np.empty(n)
+    k = 0
+    draws = 0
+    while k < n:
+        draws += 1
+        if draws > max_draws:
+            raise RuntimeError(f"bubble placement failed after {max_draws} draws ({k}/{n})")
+        R = rng.uniform(rmin, rmax)
+        xmin, xmax = x_lo + gap + R, nx - gap - R
+        ymin, ymax = gap + R, ny - gap - R
+        if xmax <= xmin or ymax <= ymin:
+            continue
+        x = rng.uniform(xmin, xmax)
+        y = rng.uniform(ymin, ymax)
+        if k:
+            d2 = (xs[:k] - x) ** 2 + (ys[:k] - y) ** 2
+            lim = rs[:k] + R + gap
+            if np.any(d2 < lim * lim):
+                continue
+        xs[k], ys[k], rs[k] = x, y, R
+        k += 1
+    return np.stack([xs, ys, rs], axis=1)
+
+
+# --------------------------------------------------------------------------
+# Workloads
+def shock_tube_1d(nx: int = 1000, ny: int = 1, x0: float = 0.7, length: float = 1.0,
+                  p_left: float = 1.0e9, rho_left: float = 1000.0, p_right: float = 1.0e5,
+                  rho_right: float = 1.0, t_end: float = 2.4e-4, eps: float = Z_EPS,
+                  sharp: bool = False) -> Scenario:
+    """Two-material shock tube: high-pressure water left of x0, air right of it;
+    minmod, CFL 0.5.  The air volume fraction is smeared by tanh over the cell
+    size (sharp=False) or a step at x0 (sharp=True).  The pressure is a step
+    at x0 in both cases: blending it through the smeared zone would hand the
+    air of the mixed cells an internal energy of the order of the water
+    pressure and launch a spuriously fast air shock."""
+    dx = length / nx
+    prim = _blank(nx, ny)
+    xc = (np.arange(nx, dtype=np.float64) + 0.5) * dx
+    if sharp:
+        w = (xc > x0).astype(np.float64)
+    else:
+        w = 0.5 * (1.0 + np.tanh((xc - x0) / dx))
+    prim[0] = w[None, :]
+    prim[1] = rho_right
+    prim[2] = rho_left
+    prim[5] = np.where(xc > x0, p_right, p_left)[None, :]
+    return Scenario("shock_tube_1d", nx, ny, dx, dx, _finish(prim, eps), cfl=0.5,
+                    limiter="minmod", t_end=t_end,
+                    meta=dict(x0=x0, p_left=p_left, rho_left=rho_left, p_right=p_right,
+                              rho_right=rho_right))
+
+
+def single_bubble(nx: int = 1024, ny: int = 512, dx: float = 1.0e-5, radius: float = 64.0,
+                  centre=(400.0, 256.0), shock_x: float = 320.0, p_shock: float = 1.0e9,
+                  steps: int = 2000, eps: float = Z_EPS) -> Scenario:
+    """One air bubble in water hit by a planar 1 GPa shock; the shocked water
+    occupies x < shock_x (cell units).  Mirror symmetric about y = ny/2 when
+    the centre lies on it."""
+    prim = _blank(nx, ny)
+    rho1, u1, S = stiffened_gas_shock(p_shock)
+    ns = int(shock_x)
+    prim[2, :, :ns] = rho1
+    prim[3, :, :ns] = u1
+    prim[5, :, :ns] = p_shock
+    _paint_bubble(prim[0], centre[0], centre[1], radius)
+    return Scenario("single_bubble", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                    steps=steps, meta=dict(p_shock=p_shock, shock_speed=S, rho1=rho1, u1=u1,
+                                           radius=radius, centre=centre, shock_x=shock_x))
+
+
+def random_bubbles(nx: int, ny: int, nbubbles: int, rmin: float, rmax: float, gap: float,
+                   seed: int, dx: float = 1.0e-5, p_shock: float = 1.0e9, strip: int = 16,
+                   steps: int = 0, name: str = "random_bubbles", eps: float = Z_EPS,
+                   bubbles: np.ndarray | None = None) -> Scenario:
+    """Random air-bubble field in water; a planar shock enters from x = 0 out of
+    a shocked strip of `strip` cells.  Bubbles are placed by seeded rejection
+    sampling (numpy PCG64 stream of `seed`)."""
+    if bubbles is None:
+        rng = np.random.default_rng(seed)
+        bubbles = place_bubbles(rng, nbubbles, nx, ny, rmin, rmax, gap, x_lo=float(strip))
+    prim = _blank(nx, ny)
+    rho1, u1, S = stiffened_gas_shock(p_shock)
+    prim[2, :, :strip] = rho1
+    prim[3, :, :strip] = u1
+    prim[5, :, :strip] = p_shock
+    for x, y, R in bubbles:
+        _paint_bubble(prim[0], x, y, R)
+    porosity = float(np.pi * np.sum(bubbles[:, 2] ** 2) / (nx * ny))
+    return Scenario(name, nx, ny, dx, dx, _finish(prim, eps), cfl=0.4, steps=steps,
+                    meta=dict(seed=seed, p_shock=p_shock, shock_speed=S, porosity=porosity,
+                              nbubbles=len(bubbles), bubbles=bubbles))
+
+
+def random_field_4096(seed: int = SEEDS["random_4096x2048"]) -> Scenario:
+    """4096 x 2048, 200 bubbles, radius U[20, 40] cells, edge gap >= 4, 5000 steps."""
+    return random_bubbles(4096, 2048, 200, 20.0, 40.0, 4.0, seed, steps=5000,
+                          name="random_4096x2048")
+
+
+def roofline_8192(seed: int = SEEDS["roofline_8192"], n: int = 8192) -> Scenario:
+    """8192 x 8192, 2000 bubbles, radius U[16, 48] cells, edge gap >= 4, 1000 steps."""
+    return random_bubbles(n, n, 2000, 16.0, 48.0, 4.0, seed, steps=1000, name="roofline_8192")
+
+
+def serving_request(rng: np.random.Generator, sizes=(128, 256, 512), steps: int = 500,
+                    eps: float = Z_EPS) -> Scenario:
+    """One independent shock-bubble solve of the serving workload: square grid
+    drawn from `sizes`, 1-8 bubbles of radius U[0.05, 0.15] x width with edge
+    gap >= 2 cells, shock pressure U[0.5, 2] GPa; placement retried."""
+    n = int(rng.choice(sizes))
+    nb = int(rng.integers(1, 9))
+    p_shock = float(rng.uniform(0.5e9, 2.0e9))
+    sub_seed = int(rng.integers(0, 2 ** 62))
+    for attempt in range(64):
+        try:
+            sub = np.random.default_rng(sub_seed + attempt)
+            b = place_bubbles(sub, nb, n, n, 0.05 * n, 0.15 * n, 2.0, x_lo=16.0,
+                              max_draws=20000)
+            break
+        except RuntimeError:
+            continue
+    else:
+        raise RuntimeError("serving request: bubble placement failed")
+    sc = random_bubbles(n, n, nb, 0.0, 0.0, 2.0, 0, p_shock=p_shock, steps=steps,
+                        name=f"serving_{n}", eps=eps, bubbles=b)
+    sc.meta["p_shock"] = p_shock
+    return sc
+
+
+def serving_workload(nreq: int = 256, seed: int = SEEDS["serving"], sizes=(128, 256, 512),
+                     steps: int = 500):
+    """The list of serving requests, reproducible from `seed`."""
+    rng = np.random.default_rng(seed)
+    return [serving_request(rng, sizes=sizes, steps=steps) for _ in range(nreq)]
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = SEEDS["serving"]) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate (1/s)."""
+    rng = np.random.default_rng(seed + 1)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def uniform_state(nx: int, ny: int, dx: float = 1.0e-3, z1: float = Z_EPS,
+                  rho1: float = RHO_AIR, rho2: float = RHO_WATER, u: float = 0.0,
+                  v: float = 0.0, p: float = P_AMBIENT) -> np.ndarray:
+    prim = np.empty((6, ny, nx), dtype=np.float64)
+    prim[0], prim[1], prim[2], prim[3], prim[4], prim[5] = z1, rho1, rho2, u, v, p
+    return prim
