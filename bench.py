@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Throughput of the two-fluid finite-volume step on one MI355X.
+
+Workload (default): the 8192 x 8192 roofline case -- 2000 seeded air bubbles
+(radius U[16, 48] cells) in water hit by a planar 1 GPa shock, transmissive
+walls, CFL 0.4 -- advanced in FP64, FP32-bulk/FP64-accumulate and pure FP32.
+A step is one pass of the whole hot path: CFL time step from the device-side
+maximum, both split sweeps (MUSCL-Hancock + HLLC + non-conservative z1 term),
+the pointwise stage and the next step's CFL maximum.  Inputs are resident in
+HBM before the timed region starts.
+
+Prints ONE JSON line.  The FP64 mode is the headline `value`; the other modes
+are reported under "modes".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_CELL = {"fp64": 96, "fp32_fp64acc": 96, "fp32": 48}   # 1 read + 1 write of 6 planes
+DTYPE = {"fp64": "f64", "fp32_fp64acc": "f32/f64", "fp32": "f32"}
+METRIC = "cell-updates/s/GPU FP32 vs FP64 (+% HBM roofline); batched p50/p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("meso_kernels.hip", "meso_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(mode: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "step_kernel_roofline_8192_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    m = d.get("modes", {}).get(mode)
+    return None if m is None else m.get("hbm_bytes_per_launch")
+
+
+def run_mode(sc, prec, steps, warmup, ref=None):
+    import torch
+    from paper_1905_05727_amd import meso
+    s = meso.Solver.from_scenario(sc, precision=prec)
+    info = s.launch_info()
+    s.run_steps(warmup)
+    s.sync()
+    s.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run_steps(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = s.kernel_time()
+    t_sim, nstep, _ = s.time()
+    out = {"s": t1 - t0, "kernel_ms_avg": kms / max(launches, 1), "launches": launches,
+           "t_sim": t_sim, "step": nstep, "launch": info}
+    out["fields"] = {k: s.read_field(k) for k in ("rho", "p")}
+    s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(sc, nsteps):
+    import oracle
+    o = oracle.Oracle(oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl))
+    o.set_primitive(sc.prim)
+    t0 = time.perf_counter()
+    o.run(nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": sc.nx * sc.ny * nsteps / dt, "unit": "cell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {nsteps} steps of the full {sc.nx}x{sc.ny} workload, FP64 "
+                      f"oracle ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=8192, help="grid size (n x n)")
+    ap.add_argument("--modes", default="fp64,fp32_fp64acc,fp32")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs one domain on one GPU; multi-GPU runs are not "
+              "part of this build (see the sharding design notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1905_05727_amd import scenario
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+
+    t = time.perf_counter()
+    sc = scenario.roofline_8192(n=args.n)
+    log(f"scenario {sc.name} {sc.nx}x{sc.ny}: {sc.meta['nbubbles']} bubbles, porosity "
+        f"{sc.meta['porosity']:.3f} ({time.perf_counter() - t:.1f} s)")
+    modes = [m for m in args.modes.split(",") if m]
+    N = sc.nx * sc.ny
+    res = {}
+    for m in modes:
+        log(f"mode {m}: warmup {args.warmup}, timing {args.steps} steps")
+        res[m] = run_mode(sc, m, args.steps, args.warmup)
+        r = res[m]
+        log(f"  {N * args.steps / r['s'] / 1e9:.2f} G cell-updates/s, kernel "
+            f"{r['kernel_ms_avg']:.3f} ms/launch, t_sim {r['t_sim']:.3e}")
+
+    mode_out = {}
+    ref = res.get("fp64")
+    for m, r in res.items():
+        cups = N * args.steps / r["s"]
+        ach = BYTES_PER_CELL[m] * N / (r["kernel_ms_avg"] * 1e-3) / 1e9
+        d = {"value": cups, "ms_per_step": 1e3 * r["s"] / args.steps,
+             "kernel_ms": r["kernel_ms_avg"], "hbm_algorithmic_GBs": ach,
+             "roofline_frac": ach / HBM_PEAK_GBS, "dtype": DTYPE[m]}
+        if ref is not None and m != "fp64":
+            for k in ("rho", "p"):
+                d[f"rel_l1_{k}_vs_fp64"] = float(np.abs(r["fields"][k] - ref["fields"][k]).sum()
+                                                 / np.abs(ref["fields"][k]).sum())
+        mode_out[m] = d
+
+    head = "fp64" if "fp64" in res else modes[0]
+    h = mode_out[head]
+    r = res[head]
+    line = {
+        "metric": METRIC,
+        "value": h["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": h["dtype"],
+        "data": "synthetic",
+        "config": {"workload": f"roofline case {sc.nx}x{sc.ny}: {sc.meta['nbubbles']} air "
+                               f"bubbles R~U[16,48] cells in water, 1 GPa planar shock, "
+                               f"CFL 0.4, seed {sc.meta['seed']}",
+                   "cells": N, "precision": head, "parallelism": "single GPU",
+                   "launch": r["launch"]},
+        "roofline": {"bound": "hbm", "achieved": h["hbm_algorithmic_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": h["roofline_frac"],
+                     "traffic": traffic_from_profiles(head),
+                     "kernel": "step_kernel (fused x/y sweep)",
+                     "bytes_per_cell": BYTES_PER_CELL[head]},
+        "modes": mode_out,
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_steps} steps")
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * meso.h -- C ABI of the MI355X two-fluid shock/bubble solver.
+ *
+ * The solver advances the inert two-phase Euler system of Eq. (1) (Sec. 2.1:
+ * partial densities z1 rho1 and z2 rho2, momentum, total energy, and the
+ * non-conservative advection of the air volume fraction z1) with the
+ * pressure-equilibrium closure of Sec. 2.1 and stiffened-gas phases (the
+ * Mie-Grueneisen form of Eq. (2) with constant reference terms, Sec. 2.2;
+ * air as an ideal gas, Table 2).  The scheme is that of Sec. 3:
+ * MUSCL-Hancock reconstruction with a van Leer (or minmod) slope limiter, HLLC
+ * fluxes, dimensionally split sweeps, a CFL time step, and the pointwise stage
+ * of the Strang split (with no reaction: z1 kept in [eps, 1 - eps]).
+ *
+ * The calls follow the paper's statement of the problem (Sec. 2.4 and Sec. 3):
+ * a rectangular uniform grid with two materials, initial fields set once,
+ * the state kept resident on the device and advanced to a final time, with
+ * field output on request (host/device transfers only at initialisation and
+ * output).
+ *
+ * Conventions for every call:
+ *  - All functions return an mf_status (0 = success, negative = error) and
+ *    never throw or abort.  A NULL solver/server handle gives
+ *    MF_E_INVALID_ARG.
+ *  - Host buffers are owned by the caller and only accessed during the call.
+ *  - Field arrays are planes of nx*ny doubles, row-major with x fastest
+ *    (index j*nx + i).  Primitive sets are 6 consecutive planes
+ *    (z1, rho1, rho2, u, v, p); conserved sets are 6 consecutive planes
+ *    (z1 rho1, z2 rho2, rho u, rho v, rho E, z1).
+ *  - Stepping calls only enqueue work on the solver's stream and return;
+ *    errors found on the device (non-finite state, rho <= 0, rho c^2 <= 0)
+ *    are latched and reported by the next synchronising call
+ *    (mf_sync, mf_read_*, mf_get_time, mf_run_to_time) as
+ *    MF_E_NONFINITE_STATE.  After such an error the state is unspecified;
+ *    the solver may be re-set (mf_set_*) or destroyed.
+ *  - One solver is used from one host thread at a time.
+ */
+#ifndef MESO_H
+#define MESO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MF_OK                 0
+#define MF_E_INVALID_ARG     -1   /* bad argument; nothing was changed      */
+#define MF_E_OUT_OF_MEMORY   -2   /* device allocation or workspace too small */
+#define MF_E_NONFINITE_STATE -3   /* NaN/Inf, rho <= 0 or rho c^2 <= 0 found */
+#define MF_E_DEVICE          -5   /* HIP runtime error (launch, copy, sync)  */
+#define MF_E_NOT_READY       -6   /* result asked for before it exists       */
+#define MF_E_BUSY            -7   /* server has no free slot or budget       */
+
+/* Precision modes: arithmetic of the flux path / storage of the state. */
+#define MF_FP64          0  /* FP64 everywhere; equals the FP64 contract bit for bit */
+#define MF_FP32_FP64ACC  1  /* FP64 state, pressure inversion and update;
+                               FP32 reconstruction, predictor and HLLC         */
+#define MF_FP32          2  /* FP32 state and arithmetic                       */
+
+/* Boundary conditions (Sec. 2.4, Fig. 1): transmissive = zero-order
+ * extrapolation of the edge cell; periodic = wrap (must be set on both
+ * sides of an axis). */
+#define MF_BC_TRANSMISSIVE 0
+#define MF_BC_PERIODIC     1
+
+/* Slope limiters (Sec. 3). */
+#define MF_LIM_VANLEER 0
+#define MF_LIM_MINMOD  1
+
+/* Fields for mf_read_field. 0-5: conserved, 6-10: derived. */
+#define MF_Z1RHO1 0
+#define MF_Z2RHO2 1
+#define MF_RHOU   2
+#define MF_RHOV   3
+#define MF_RHOE   4
+#define MF_Z1     5
+#define MF_RHO    6
+#define MF_U      7
+#define MF_V      8
+#define MF_P      9
+#define MF_C     10
+
+/* A stiffened-gas phase: p = (gamma - 1) rho e - gamma p_inf (Eq. (2) with
+ * constant reference terms).  Air: p_inf = 0. */
+typedef struct {
+    double gamma;
+    double p_inf;
+} mf_material;
+
+/* Uniform Cartesian grid (Sec. 3), cell sizes in metres. */
+typedef struct {
+    int32_t nx, ny;
+    double dx, dy;
+    int32_t bc_xlo, bc_xhi, bc_ylo, bc_yhi;
+} mf_grid;
+
+/* Scheme options.  cfl in (0, 1]; z_floor in [0, 0.5) is the eps of the
+ * pointwise stage; limiter MF_LIM_*; precision MF_FP*; fused = 1 runs the
+ * two split sweeps of a step in one kernel (one read and one write of the
+ * state), 0 runs one kernel per sweep (for cross-checking). */
+typedef struct {
+    double cfl;
+    double z_floor;
+    int32_t limiter;
+    int32_t precision;
+    int32_t fused;
+    int32_t reserved;
+} mf_options;
+
+typedef struct mf_solver mf_solver;
+
+/* Device bytes a solver of this grid and precision needs (two state copies
+ * plus a 256-byte control block).  0 for an invalid grid. */
+size_t mf_workspace_bytes(const mf_grid *grid, int32_t precision);
+
+/* Create a solver on the current HIP device.
+ *  mat[0] = phase 1 (gas, the cavity content), mat[1] = phase 2 (liquid).
+ *  dev_workspace: device memory of at least mf_workspace_bytes() bytes,
+ *    256-byte aligned, owned by the caller and kept alive until
+ *    mf_destroy; or NULL, then the library allocates and frees it.
+ *  hip_stream: hipStream_t the solver enqueues all work on (NULL = the null
+ *    stream); owned by the caller, must outlive the solver.
+ * Errors: MF_E_INVALID_ARG (bad grid/material/option, workspace too small or
+ * misaligned), MF_E_OUT_OF_MEMORY, MF_E_DEVICE.  The state is zero until set. */
+int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_options *opt,
+                  void *dev_workspace, size_t ws_bytes, void *hip_stream, mf_solver **out);
+
+/* Set the state from host primitive planes (z1, rho1, rho2, u, v, p), 6*nx*ny
+ * doubles, converted to conserved variables on the device by the closure of
+ * Sec. 2.1.  Resets the latched error and computes the first time step's CFL
+ * bound.  Synchronises the stream.  Time and step count are unchanged. */
+int32_t mf_set_primitive(mf_solver *s, const double *prim);
+
+/* Set the state from host conserved planes (6*nx*ny doubles); in MF_FP32 mode
+ * the values are rounded to float.  Same side effects as mf_set_primitive. */
+int32_t mf_set_conserved(mf_solver *s, const double *cons);
+
+/* Set the time and the step counter (its parity selects the sweep order:
+ * x then y on even steps, y then x on odd steps).  Synchronises. */
+int32_t mf_set_time(mf_solver *s, double t, int64_t step);
+
+/* Enqueue one step.  dt > 0: use this time step; dt <= 0: dt = CFL / max
+ * signal speed of the current state (computed on the device; no host round
+ * trip).  Does not synchronise. */
+int32_t mf_step(mf_solver *s, double dt);
+
+/* Enqueue nsteps CFL steps (nsteps >= 0).  Does not synchronise. */
+int32_t mf_run_steps(mf_solver *s, int64_t nsteps);
+
+/* Advance with CFL steps until t == t_end (the last step is shortened to land
+ * on t_end exactly) or max_steps steps were taken.  Polls the device time
+ * every few steps; synchronises before returning.  *steps_taken (may be NULL)
+ * receives the number of steps taken by this call. */
+int32_t mf_run_to_time(mf_solver *s, double t_end, int64_t max_steps, int64_t *steps_taken);
+
+/* Wait for all enqueued work; MF_E_NONFINITE_STATE if an error was latched. */
+int32_t mf_sync(mf_solver *s);
+
+/* Copy one field (MF_* field id) as nx*ny doubles to host_out (count must be
+ * nx*ny).  Derived fields use the closure of Sec. 2.1.  Synchronises. */
+int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t count);
+
+/* Copy the 6 conserved planes (6*nx*ny doubles) to host_out.  Synchronises. */
+int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count);
+
+/* Time, completed step count and the last time step.  Synchronises. */
+int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt);
+
+/* Kernel timing: when enabled, every step kernel launch is bracketed by HIP
+ * events on the solver's stream.  mf_kernel_time synchronises and returns the
+ * summed duration (ms) and launch count of the state-update kernels since
+ * the last reset (enable resets).  Costs two event records per launch. */
+int32_t mf_enable_timing(mf_solver *s, int32_t enable);
+int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches);
+
+/* Kernel launch geometry of the state-update kernel for this solver:
+ * workgroups, threads per workgroup, and the number of cells one workgroup
+ * writes (strip width x segment height). */
+int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int32_t *tile_w,
+                       int32_t *tile_h);
+
+/* Release the solver (and the workspace if the library allocated it).
+ * Synchronises its stream first. */
+int32_t mf_destroy(mf_solver *s);
+
+/* Static text for a status code. */
+const char *mf_status_str(int32_t status);
+
+/* Library version string. */
+const char *mf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESO_H */

@@ -1,0 +1,417 @@
+// meso_api.hip -- host side of the C ABI declared in include/meso.h.
+//
+// Owns the device workspace layout (control block + two pitched state
+// copies), enqueues the kernels of a step on the caller's stream and turns
+// latched device errors into status codes at synchronising calls.
+
+#include "meso.h"
+#include "meso_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+using meso::Control;
+using meso::Desc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool grid_ok(const mf_grid *g) {
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1) return false;
+    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !isfinite(g->dx) || !isfinite(g->dy)) return false;
+    const int32_t b[4] = {g->bc_xlo, g->bc_xhi, g->bc_ylo, g->bc_yhi};
+    for (int i = 0; i < 4; ++i)
+        if (b[i] != MF_BC_TRANSMISSIVE && b[i] != MF_BC_PERIODIC) return false;
+    if ((g->bc_xlo == MF_BC_PERIODIC) != (g->bc_xhi == MF_BC_PERIODIC)) return false;
+    if ((g->bc_ylo == MF_BC_PERIODIC) != (g->bc_yhi == MF_BC_PERIODIC)) return false;
+    if ((long long)g->nx * g->ny > (1LL << 40)) return false;
+    return true;
+}
+
+size_t elem_size(int32_t prec) { return prec == MF_FP32 ? 4 : 8; }
+
+int pitch_of(int nx) { return (int)round_up((size_t)nx, 64); }
+
+size_t state_bytes(const mf_grid *g, int32_t prec) {
+    return round_up((size_t)6 * pitch_of(g->nx) * (size_t)g->ny * elem_size(prec), kAlign);
+}
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mf_solver {
+    Desc d;
+    mf_grid grid;
+    mf_material mat[2];
+    mf_options opt;
+    hipStream_t stream;
+    void *ws;
+    size_t ws_bytes;
+    bool own_ws;
+    long long host_step;  // completed steps once all enqueued work has run
+    bool timing;
+    std::vector<EventPair> ev;
+    size_t ev_used;
+};
+
+namespace {
+
+int32_t dev_err(hipError_t e) { return e == hipSuccess ? MF_OK : MF_E_DEVICE; }
+
+// Index of the state copy that holds the state after `step` completed steps.
+int state_index(const mf_solver *s, long long step) {
+    return s->opt.fused ? (int)(step & 1) : 0;
+}
+
+int32_t read_control(mf_solver *s, Control *c) {
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return MF_E_DEVICE;
+    if (hipMemcpy(c, s->d.ctl, sizeof(Control), hipMemcpyDeviceToHost) != hipSuccess)
+        return MF_E_DEVICE;
+    s->host_step = c->step;
+    return MF_OK;
+}
+
+// After the state changed from the host: reset the control block and compute
+// the CFL maximum of the new state for the next step.
+int32_t restart(mf_solver *s, double t, long long step) {
+    hipError_t e = meso::launch_init_control(s->d, t, step, s->stream);
+    if (e == hipSuccess) e = meso::launch_reduce(s->d, s->opt.precision, state_index(s, step),
+                                                 s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    s->host_step = step;
+    return dev_err(e);
+}
+
+int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
+    hipError_t e = meso::launch_dt(s->d, s->opt.cfl, s->grid.dx, s->grid.dy, dt_fixed, t_end,
+                                   s->stream);
+    if (e != hipSuccess) return MF_E_DEVICE;
+    const long long n = s->host_step;
+    const int prec = s->opt.precision, lim = s->opt.limiter;
+    EventPair *ep = nullptr;
+    if (s->timing) {
+        if (s->ev_used == s->ev.size()) {
+            EventPair p;
+            if (hipEventCreate(&p.a) != hipSuccess) return MF_E_DEVICE;
+            if (hipEventCreate(&p.b) != hipSuccess) return MF_E_DEVICE;
+            s->ev.push_back(p);
+        }
+        ep = &s->ev[s->ev_used++];
+        if (hipEventRecord(ep->a, s->stream) != hipSuccess) return MF_E_DEVICE;
+    }
+    if (s->opt.fused) {
+        const int src = (int)(n & 1);
+        e = meso::launch_step(s->d, prec, lim, (n & 1) ? meso::kYX : meso::kXY, 1, src,
+                              s->stream);
+    } else {
+        // buffer 0 -> 1 in the first sweep, 1 -> 0 in the second
+        const int first = (n & 1) ? meso::kY : meso::kX;
+        const int second = (n & 1) ? meso::kX : meso::kY;
+        e = meso::launch_step(s->d, prec, lim, first, 0, 0, s->stream);
+        if (e == hipSuccess) e = meso::launch_step(s->d, prec, lim, second, 1, 1, s->stream);
+    }
+    if (e != hipSuccess) return MF_E_DEVICE;
+    if (ep && hipEventRecord(ep->b, s->stream) != hipSuccess) return MF_E_DEVICE;
+    s->host_step = n + 1;
+    return MF_OK;
+}
+
+int choose_seg_h(int nstrips, int ny) {
+    const char *env = getenv("MESO_SEG_H");
+    if (env) {
+        const int v = atoi(env);
+        if (v >= 1) return v;
+    }
+    int h = 128;
+    while (h > 16 && (long long)nstrips * ((ny + h - 1) / h) < 512) h >>= 1;
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mf_workspace_bytes(const mf_grid *grid, int32_t precision) {
+    if (!grid_ok(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
+    return kAlign + 2 * state_bytes(grid, precision);
+}
+
+int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_options *opt,
+                  void *dev_workspace, size_t ws_bytes, void *hip_stream, mf_solver **out) {
+    if (!out) return MF_E_INVALID_ARG;
+    *out = nullptr;
+    if (!grid_ok(grid) || !mat || !opt) return MF_E_INVALID_ARG;
+    for (int k = 0; k < 2; ++k)
+        if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
+            !isfinite(mat[k].p_inf))
+            return MF_E_INVALID_ARG;
+    if (!(opt->cfl > 0.0) || !(opt->cfl <= 1.0)) return MF_E_INVALID_ARG;
+    if (!(opt->z_floor >= 0.0) || !(opt->z_floor < 0.5)) return MF_E_INVALID_ARG;
+    if (opt->limiter != MF_LIM_VANLEER && opt->limiter != MF_LIM_MINMOD) return MF_E_INVALID_ARG;
+    if (opt->precision < MF_FP64 || opt->precision > MF_FP32) return MF_E_INVALID_ARG;
+    if (opt->fused != 0 && opt->fused != 1) return MF_E_INVALID_ARG;
+    const size_t need = mf_workspace_bytes(grid, opt->precision);
+    if (dev_workspace && (ws_bytes < need || ((uintptr_t)dev_workspace % kAlign) != 0))
+        return MF_E_INVALID_ARG;
+
+    mf_solver *s = new (std::nothrow) mf_solver();
+    if (!s) return MF_E_OUT_OF_MEMORY;
+    s->grid = *grid;
+    s->mat[0] = mat[0];
+    s->mat[1] = mat[1];
+    s->opt = *opt;
+    s->stream = (hipStream_t)hip_stream;
+    s->own_ws = dev_workspace == nullptr;
+    s->ws_bytes = need;
+    s->timing = false;
+    s->ev_used = 0;
+    if (s->own_ws) {
+        if (hipMalloc(&s->ws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return MF_E_OUT_OF_MEMORY;
+        }
+    } else {
+        s->ws = dev_workspace;
+    }
+    char *base = (char *)s->ws;
+    Desc &d = s->d;
+    d.ctl = (Control *)base;
+    d.buf[0] = base + kAlign;
+    d.buf[1] = base + kAlign + state_bytes(grid, opt->precision);
+    d.nx = grid->nx;
+    d.ny = grid->ny;
+    d.pitch = pitch_of(grid->nx);
+    d.plane = (long long)d.pitch * grid->ny;
+    d.bc_xlo = grid->bc_xlo;
+    d.bc_xhi = grid->bc_xhi;
+    d.bc_ylo = grid->bc_ylo;
+    d.bc_yhi = grid->bc_yhi;
+    d.nstrips = (grid->nx + meso::kTileW - 1) / meso::kTileW;
+    d.seg_h = choose_seg_h(d.nstrips, grid->ny);
+    d.nsegs = (grid->ny + d.seg_h - 1) / d.seg_h;
+    d.idx = 1.0 / grid->dx;
+    d.idy = 1.0 / grid->dy;
+    d.zlo = opt->z_floor;
+    d.zhi = 1.0 - opt->z_floor;
+    d.g1 = 1.0 / (mat[0].gamma - 1.0);
+    d.g2 = 1.0 / (mat[1].gamma - 1.0);
+    d.h1 = (mat[0].gamma * mat[0].p_inf) * d.g1;
+    d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
+
+    hipError_t e = hipMemsetAsync(s->ws, 0, need, s->stream);
+    if (e == hipSuccess) e = meso::launch_init_control(d, 0.0, 0, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        if (s->own_ws) (void)hipFree(s->ws);
+        delete s;
+        return MF_E_DEVICE;
+    }
+    s->host_step = 0;
+    *out = s;
+    return MF_OK;
+}
+
+static int32_t set_state(mf_solver *s, const double *host, bool prim) {
+    if (!s || !host) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    const size_t n = (size_t)s->grid.nx * s->grid.ny * 6;
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MF_E_OUT_OF_MEMORY;
+    }
+    hipError_t e = hipMemcpy(tmp, host, n * sizeof(double), hipMemcpyHostToDevice);
+    const int dst = state_index(s, c.step);
+    if (e == hipSuccess)
+        e = prim ? meso::launch_prim_to_cons(s->d, s->opt.precision, dst, tmp, s->stream)
+                 : meso::launch_cons_from_f64(s->d, s->opt.precision, dst, tmp, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return MF_E_DEVICE;
+    return restart(s, c.t, c.step);
+}
+
+int32_t mf_set_primitive(mf_solver *s, const double *prim) { return set_state(s, prim, true); }
+
+int32_t mf_set_conserved(mf_solver *s, const double *cons) { return set_state(s, cons, false); }
+
+int32_t mf_set_time(mf_solver *s, double t, int64_t step) {
+    if (!s || !isfinite(t) || step < 0) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    const int from = state_index(s, c.step), to = state_index(s, step);
+    if (from != to) {
+        const size_t b = state_bytes(&s->grid, s->opt.precision);
+        if (hipMemcpyAsync(s->d.buf[to], s->d.buf[from], b, hipMemcpyDeviceToDevice,
+                           s->stream) != hipSuccess)
+            return MF_E_DEVICE;
+    }
+    return restart(s, t, step);
+}
+
+int32_t mf_step(mf_solver *s, double dt) {
+    if (!s || !(dt == dt) || isinf(dt)) return MF_E_INVALID_ARG;
+    return enqueue_step(s, dt > 0.0 ? dt : 0.0, 0.0);
+}
+
+int32_t mf_run_steps(mf_solver *s, int64_t nsteps) {
+    if (!s || nsteps < 0) return MF_E_INVALID_ARG;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        int32_t st = enqueue_step(s, 0.0, 0.0);
+        if (st != MF_OK) return st;
+    }
+    return MF_OK;
+}
+
+int32_t mf_run_to_time(mf_solver *s, double t_end, int64_t max_steps, int64_t *steps_taken) {
+    if (steps_taken) *steps_taken = 0;
+    if (!s || !(t_end > 0.0) || !isfinite(t_end) || max_steps < 0) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (c.err) return MF_E_NONFINITE_STATE;
+    const long long start = c.step;
+    long long chunk = 8;
+    while (c.t < t_end && c.step - start < max_steps) {
+        const long long left = max_steps - (c.step - start);
+        const long long k = chunk < left ? chunk : left;
+        for (long long i = 0; i < k; ++i) {
+            st = enqueue_step(s, 0.0, t_end);
+            if (st != MF_OK) return st;
+        }
+        st = read_control(s, &c);
+        if (st != MF_OK) return st;
+        if (c.err) break;
+        if (chunk < 256) chunk *= 2;
+    }
+    if (steps_taken) *steps_taken = c.step - start;
+    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+}
+
+int32_t mf_sync(mf_solver *s) {
+    if (!s) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+}
+
+int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t count) {
+    if (!s || !host_out || field < 0 || field > MF_C) return MF_E_INVALID_ARG;
+    const size_t n = (size_t)s->grid.nx * s->grid.ny;
+    if (count != n) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (c.err) return MF_E_NONFINITE_STATE;
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MF_E_OUT_OF_MEMORY;
+    }
+    hipError_t e = meso::launch_read_field(s->d, s->opt.precision, state_index(s, c.step), field,
+                                           tmp, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(host_out, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    return dev_err(e);
+}
+
+int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count) {
+    if (!s || !host_out) return MF_E_INVALID_ARG;
+    const size_t n = (size_t)s->grid.nx * s->grid.ny;
+    if (count != 6 * n) return MF_E_INVALID_ARG;
+    for (int f = 0; f < 6; ++f) {
+        int32_t st = mf_read_field(s, f, host_out + f * n, n);
+        if (st != MF_OK) return st;
+    }
+    return MF_OK;
+}
+
+int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt) {
+    if (!s) return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (t) *t = c.t;
+    if (step) *step = c.step;
+    if (last_dt) *last_dt = c.dt;
+    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+}
+
+int32_t mf_enable_timing(mf_solver *s, int32_t enable) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return MF_E_DEVICE;
+    s->timing = enable != 0;
+    s->ev_used = 0;
+    return MF_OK;
+}
+
+int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return MF_E_DEVICE;
+    double tot = 0.0;
+    for (size_t i = 0; i < s->ev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, s->ev[i].a, s->ev[i].b) != hipSuccess) return MF_E_DEVICE;
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)s->ev_used;
+    s->ev_used = 0;
+    return MF_OK;
+}
+
+int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int32_t *tile_w,
+                       int32_t *tile_h) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (workgroups) *workgroups = (int64_t)s->d.nstrips * s->d.nsegs;
+    if (threads) *threads = meso::kThreads;
+    if (tile_w) *tile_w = meso::kTileW;
+    if (tile_h) *tile_h = s->d.seg_h;
+    return MF_OK;
+}
+
+int32_t mf_destroy(mf_solver *s) {
+    if (!s) return MF_E_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    for (auto &p : s->ev) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    if (s->own_ws) (void)hipFree(s->ws);
+    delete s;
+    return dev_err(e);
+}
+
+const char *mf_status_str(int32_t status) {
+    switch (status) {
+        case MF_OK: return "ok";
+        case MF_E_INVALID_ARG: return "invalid argument";
+        case MF_E_OUT_OF_MEMORY: return "out of device memory";
+        case MF_E_NONFINITE_STATE: return "non-finite or non-physical state";
+        case MF_E_DEVICE: return "HIP runtime error";
+        case MF_E_NOT_READY: return "not ready";
+        case MF_E_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+const char *mf_version(void) { return "meso 0.1 gfx950"; }
+
+}  // extern "C"

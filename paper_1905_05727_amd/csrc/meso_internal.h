@@ -1,0 +1,67 @@
+// meso_internal.h -- device-side layout shared by the HIP kernels and the
+// host side of the C ABI (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace meso {
+
+// Step kernel geometry: one workgroup = one wave64 x 4 = 256 threads, thread t
+// owns column x0 - 2 + t of a strip; the two columns on each side are the
+// stencil halo of a sweep, so a strip writes 252 columns.
+constexpr int kThreads = 256;
+constexpr int kHalo = 2;
+constexpr int kTileW = kThreads - 2 * kHalo;
+
+// Precision modes (same numbering as MF_FP64 / MF_FP32_FP64ACC / MF_FP32).
+enum { kP64 = 0, kPMix = 1, kP32 = 2 };
+// Step kernel variants: fused x-then-y, fused y-then-x, single x sweep,
+// single y sweep.
+enum { kXY = 0, kYX = 1, kX = 2, kY = 3 };
+
+// Device control block of one solve: time, step counter, the CFL maximum of
+// the state (two slots, alternating with the step parity), latched errors.
+struct alignas(256) Control {
+    double t;
+    double dt;
+    double lam_x, lam_y;     // dt/dx, dt/dy of the step being executed
+    double hl_x, hl_y;       // 0.5 * lam
+    unsigned long long smax_bits[2];  // bit pattern of the max signal speed / h
+    long long step;          // completed steps
+    long long step_exec;     // index of the step being executed
+    int skip;                // 1: the enqueued step does nothing
+    int err;                 // latched error bits (1 = bad state)
+};
+
+// Everything a step kernel needs to know about one solve.
+struct Desc {
+    void *buf[2];            // two state copies, 6 planes each
+    Control *ctl;
+    int nx, ny;
+    int pitch;               // elements per row
+    int seg_h;               // rows per workgroup segment
+    long long plane;         // elements per plane
+    int bc_xlo, bc_xhi, bc_ylo, bc_yhi;
+    int nstrips, nsegs;
+    double idx, idy;         // 1/dx, 1/dy
+    double zlo, zhi;         // eps, 1 - eps of the pointwise stage
+    double g1, g2, h1, h2;   // mixture constants 1/(gamma-1), gamma pinf/(gamma-1)
+};
+
+// Launchers (meso_kernels.hip).  All enqueue on `st` and return the launch
+// status.  `prec` is kP64 / kPMix / kP32, `lim` the limiter id.
+hipError_t launch_init_control(const Desc &d, double t, long long step, hipStream_t st);
+hipError_t launch_prim_to_cons(const Desc &d, int prec, int dst, const double *prim,
+                               hipStream_t st);
+hipError_t launch_cons_from_f64(const Desc &d, int prec, int dst, const double *cons,
+                                hipStream_t st);
+hipError_t launch_reduce(const Desc &d, int prec, int src, hipStream_t st);
+hipError_t launch_dt(const Desc &d, double cfl, double dx, double dy, double dt_fixed,
+                     double t_end, hipStream_t st);
+hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+                       hipStream_t st);
+hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double *out,
+                             hipStream_t st);
+
+}  // namespace meso

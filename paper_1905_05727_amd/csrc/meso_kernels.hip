@@ -1,0 +1,713 @@
+// meso_kernels.hip -- gfx950 kernels of the two-fluid finite-volume update.
+//
+// Equations: inert part of Eq. (1) (Sec. 2.1) -- partial densities, momentum,
+// total energy, non-conservative advection of the air volume fraction z1 --
+// with the pressure-equilibrium closure of Sec. 2.1 and stiffened-gas phases
+// (Eq. (2) with constant reference terms, Sec. 2.2).  Scheme of Sec. 3:
+// MUSCL-Hancock in primitive variables, van Leer or minmod slopes, HLLC flux
+// with the HLLC-consistent interface velocity for the z1 term, dimensionally
+// split sweeps (x then y on even steps, y then x on odd ones), CFL time step
+// and the pointwise stage of the Strang split (z1 clamp when inert).
+//
+// Data layout in HBM: structure of arrays, 6 planes (z1 rho1, z2 rho2, rho u,
+// rho v, rho E, z1), rows padded to a multiple of 64 elements; two state copies
+// used as ping-pong buffers.
+//
+// Step kernel: a workgroup of 256 threads (4 wave64) owns a strip of 256
+// columns (252 written + 2 halo columns per side) and marches down a segment
+// of rows.  The x sweep of a row exchanges primitives, face states and fluxes
+// between neighbouring threads through LDS; the y sweep is a per-thread
+// rolling window held in registers (no exchange at all).  A fused step runs
+// both sweeps in one pass over the segment, so the state is read and written
+// once per step; the pointwise stage and the next step's CFL maximum are
+// computed in the epilogue from the values about to be stored.
+//
+// Precision is a template parameter of the same code: S is the storage /
+// accumulation type, R the type of reconstruction, predictor and Riemann
+// solver.  FP64 (S = R = double) follows the arithmetic contract operation
+// by operation (no contraction, IEEE division and square root).  The FP32
+// flux path uses the hardware reciprocal and square root.
+
+#include "meso_internal.h"
+
+#include <float.h>
+
+namespace meso {
+
+// ------------------------------------------------------------------------
+// Arithmetic helpers: exact IEEE for double, hardware approximations for float.
+template <class T> struct Ar;
+template <> struct Ar<double> {
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
+    static __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
+    static __device__ __forceinline__ double big() { return 1.0e300; }
+};
+template <> struct Ar<float> {
+    static __device__ __forceinline__ float div(float a, float b) {
+        return a * __builtin_amdgcn_rcpf(b);
+    }
+    static __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+    static __device__ __forceinline__ float sqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
+    static __device__ __forceinline__ float big() { return FLT_MAX; }
+};
+
+template <class T> struct Mix {
+    T g1, g2, h1, h2;
+};
+
+template <class T> __device__ __forceinline__ Mix<T> mix_of(const Desc &d) {
+    Mix<T> m;
+    m.g1 = (T)d.g1; m.g2 = (T)d.g2; m.h1 = (T)d.h1; m.h2 = (T)d.h2;
+    return m;
+}
+
+// Ghost-cell index map: transmissive copies the edge cell, periodic wraps.
+__device__ __forceinline__ int map_idx(int i, int n, int bc_lo, int bc_hi) {
+    if (i < 0) return bc_lo ? ((i % n) + n) % n : 0;
+    if (i >= n) return bc_hi ? i % n : n - 1;
+    return i;
+}
+
+// ------------------------------------------------------------------------
+// Closure (Sec. 2.1): sweep-frame conserved q = (a1, a2, mn, mt, E, z) to
+// primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2.
+template <class S>
+__device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[6], S &r,
+                                             S &rc2) {
+    const S rho = q[0] + q[1];
+    r = Ar<S>::rcp(rho);
+    const S un = q[2] * r;
+    const S ut = q[3] * r;
+    const S ke = S(0.5) * (q[2] * un + q[3] * ut);
+    const S rhoe = q[4] - ke;
+    const S z = q[5];
+    const S z2 = S(1) - z;
+    const S xi = z * m.g1 + z2 * m.g2;
+    const S eta = z * m.h1 + z2 * m.h2;
+    const S ixi = Ar<S>::rcp(xi);
+    const S p = (rhoe - eta) * ixi;
+    rc2 = (p * (S(1) + xi) + eta) * ixi;
+    w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
+}
+
+// Slope limiter (Sec. 3): a backward, b forward difference.
+template <class R, int LIM>
+__device__ __forceinline__ R limit(R a, R b) {
+    const R ab = a * b;
+    R s;
+    if (LIM == 1) {
+        s = (a > R(0)) ? fmin(a, b) : fmax(a, b);
+    } else {
+        s = Ar<R>::div(ab + ab, a + b);
+    }
+    return (ab > R(0)) ? s : R(0);
+}
+
+// MUSCL reconstruction and Hancock half step in primitive variables.
+template <class R, int LIM>
+__device__ __forceinline__ void face_states(const R wm[6], const R w0[6], const R wp[6], R r,
+                                            R rc2, R hl, R wl[6], R wh[6]) {
+    R d[6], s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d[c] = limit<R, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
+    const R un = w0[2];
+    s[0] = hl * (un * d[0] + w0[0] * d[2]);
+    s[1] = hl * (un * d[1] + w0[1] * d[2]);
+    s[2] = hl * (un * d[2] + r * d[4]);
+    s[3] = hl * (un * d[3]);
+    s[4] = hl * (un * d[4] + rc2 * d[2]);
+    s[5] = hl * (un * d[5]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        wl[c] = (w0[c] - R(0.5) * d[c]) - s[c];
+        wh[c] = (w0[c] + R(0.5) * d[c]) - s[c];
+    }
+}
+
+template <class R> struct Side {
+    R rho, un, ut, p, z, E;
+    R U[5], F[5];
+};
+
+template <class R>
+__device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R> &s, R &c) {
+    const R rho = w[0] + w[1];
+    const R un = w[2], ut = w[3], p = w[4], z = w[5];
+    const R z2 = R(1) - z;
+    const R xi = z * m.g1 + z2 * m.g2;
+    const R eta = z * m.h1 + z2 * m.h2;
+    c = Ar<R>::sqrt_(Ar<R>::div(p * (R(1) + xi) + eta, xi * rho));
+    const R E = (p * xi + eta) + R(0.5) * (rho * (un * un + ut * ut));
+    const R mn = rho * un;
+    s.rho = rho; s.un = un; s.ut = ut; s.p = p; s.z = z; s.E = E;
+    s.U[0] = w[0]; s.U[1] = w[1]; s.U[2] = mn; s.U[3] = rho * ut; s.U[4] = E;
+    s.F[0] = w[0] * un;
+    s.F[1] = w[1] * un;
+    s.F[2] = mn * un + p;
+    s.F[3] = mn * ut;
+    s.F[4] = (E + p) * un;
+}
+
+template <class R>
+__device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7]) {
+    const R d = S - k.un;
+    const R chi = Ar<R>::div(d, S - Ss);
+    R us[5];
+    us[0] = chi * k.U[0];
+    us[1] = chi * k.U[1];
+    us[2] = chi * (k.rho * Ss);
+    us[3] = chi * (k.rho * k.ut);
+    us[4] = chi * (k.E + (Ss - k.un) * (k.rho * Ss + Ar<R>::div(k.p, d)));
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = k.F[c] + S * (us[c] - k.U[c]);
+    out[5] = k.un + S * (chi - R(1));
+    out[6] = k.z;
+}
+
+// HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f).
+// The star state is evaluated once, for the side the contact moves away
+// from; only faces with S* == 0 exactly evaluate both sides and average.
+template <class R>
+__device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[6], R out[7]) {
+    Side<R> L, Rs;
+    R cL, cR;
+    side_eval<R>(m, wL, L, cL);
+    side_eval<R>(m, wR, Rs, cR);
+    const R SL = fmin(L.un - cL, Rs.un - cR);
+    const R SR = fmax(L.un + cL, Rs.un + cR);
+    const R dL = SL - L.un;
+    const R dR = SR - Rs.un;
+    const R Ss = Ar<R>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
+                            L.rho * dL - Rs.rho * dR);
+    const bool useL = Ss > R(0);
+    Side<R> K;
+    K.rho = useL ? L.rho : Rs.rho;
+    K.un = useL ? L.un : Rs.un;
+    K.ut = useL ? L.ut : Rs.ut;
+    K.p = useL ? L.p : Rs.p;
+    K.z = useL ? L.z : Rs.z;
+    K.E = useL ? L.E : Rs.E;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        K.U[c] = useL ? L.U[c] : Rs.U[c];
+        K.F[c] = useL ? L.F[c] : Rs.F[c];
+    }
+    R st[7];
+    star_flux<R>(K, useL ? SL : SR, Ss, st);
+    if (!(Ss > R(0)) && !(Ss < R(0))) {
+        // contact at rest relative to the face: average of both star branches
+        R a[7], b[7];
+        star_flux<R>(L, SL, Ss, a);
+        star_flux<R>(Rs, SR, Ss, b);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) st[c] = R(0.5) * (a[c] + b[c]);
+    }
+    const bool supL = SL >= R(0);
+    const bool supR = !supL && (SR <= R(0));
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = supL ? L.F[c] : (supR ? Rs.F[c] : st[c]);
+    out[5] = supL ? L.un : (supR ? Rs.un : st[5]);
+    out[6] = supL ? L.z : (supR ? Rs.z : st[6]);
+}
+
+// Update of one cell from its low- and high-face fluxes; fluxes are widened to
+// the storage type before they are differenced.
+template <class S, class R>
+__device__ __forceinline__ void update_cell(const S q[6], const R flo[7], const R fhi[7], S lam,
+                                            S qo[6]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qo[c] = q[c] - lam * ((S)fhi[c] - (S)flo[c]);
+    const S z = q[5];
+    qo[5] = z - lam * (((S)fhi[6] - z) * (S)fhi[5] - ((S)flo[6] - z) * (S)flo[5]);
+}
+
+// ------------------------------------------------------------------------
+// x sweep of one row of the strip.  All 256 threads call it (it holds
+// barriers); q: this thread's cell, qo: updated cell (valid for threads
+// 2..253; the halo threads return q unchanged).
+template <class S, class R, int LIM>
+__device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
+                                      const Mix<S> &ms, const Mix<R> &mr, R (*sWF)[kThreads],
+                                      R (*sH)[kThreads]) {
+    S w[6], r, rc2;
+    cons_to_prim<S>(ms, q, w, r, rc2);
+    R wr[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        wr[c] = (R)w[c];
+        sWF[c][t] = wr[c];
+    }
+    __syncthreads();
+    R wl[6], wh[6];
+    if (t >= 1 && t <= kThreads - 2) {
+        R wm[6], wp[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            wm[c] = sWF[c][t - 1];
+            wp[c] = sWF[c][t + 1];
+        }
+        face_states<R, LIM>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sH[c][t] = wh[c];
+    }
+    __syncthreads();
+    R f[7];
+    if (t >= 2 && t <= kThreads - 2) {
+        R whm[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) whm[c] = sH[c][t - 1];
+        hllc<R>(mr, whm, wl, f);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sWF[c][t] = f[c];
+    }
+    __syncthreads();
+    if (t >= 2 && t <= kThreads - 3) {
+        R fh[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) fh[c] = sWF[c][t + 1];
+        update_cell<S, R>(q, f, fh, lam, qo);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) qo[c] = q[c];
+    }
+    __syncthreads();
+}
+
+// y sweep as a rolling window down one column (registers only).  Rows are
+// pushed in order; after the 5th row the window yields the updated row two
+// behind the one pushed.  Values are in the y frame (normal momentum rho v).
+template <class S, class R, int LIM>
+struct YPipe {
+    S q1[6], q2[6];      // conserved rows k-1, k-2
+    R w1[6], w2[6];      // primitives rows k-1, k-2
+    R r1, c1;            // 1/rho and rho c^2 of row k-1
+    R wh2[6];            // high-face state of row k-2
+    R f2[7];             // flux through the low face of row k-2
+
+    // cnt = number of rows pushed before this one (uniform across the block)
+    __device__ __forceinline__ bool push(int cnt, const S qk[6], S qo[6], S lam, R hl,
+                                         const Mix<S> &ms, const Mix<R> &mr) {
+        S w[6], r, rc2;
+        cons_to_prim<S>(ms, qk, w, r, rc2);
+        R wk[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) wk[c] = (R)w[c];
+        bool out = false;
+        if (cnt >= 2) {
+            R wl[6], wh[6];
+            face_states<R, LIM>(w2, w1, wk, r1, c1, hl, wl, wh);
+            if (cnt >= 3) {
+                R f[7];
+                hllc<R>(mr, wh2, wl, f);
+                if (cnt >= 4) {
+                    update_cell<S, R>(q2, f2, f, lam, qo);
+                    out = true;
+                }
+#pragma unroll
+                for (int c = 0; c < 7; ++c) f2[c] = f[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) wh2[c] = wh[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            q2[c] = q1[c]; q1[c] = qk[c];
+            w2[c] = w1[c]; w1[c] = wk[c];
+        }
+        r1 = (R)r;
+        c1 = (R)rc2;
+        return out;
+    }
+};
+
+template <class S> __device__ __forceinline__ void to_yframe(const S a[6], S b[6]) {
+    b[0] = a[0]; b[1] = a[1]; b[2] = a[3]; b[3] = a[2]; b[4] = a[4]; b[5] = a[5];
+}
+
+// Pointwise stage and CFL contribution of one updated cell (U order).
+template <class S>
+__device__ __forceinline__ void epilogue(S q[6], const Mix<S> &ms, S zlo, S zhi, S idx, S idy,
+                                         S &smax, int &bad) {
+    q[5] = fmin(fmax(q[5], zlo), zhi);
+    S w[6], r, rc2;
+    cons_to_prim<S>(ms, q, w, r, rc2);
+    const S c = Ar<S>::sqrt_(rc2 * r);
+    const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
+    if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S>::big())) bad = 1;
+    else smax = fmax(smax, s);
+}
+
+// Workgroup max of the CFL bound folded into the control block.
+__device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *ctl, int slot) {
+    __shared__ double red_s[kThreads / 64];
+    __shared__ int red_b[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        smax = fmax(smax, __shfl_xor(smax, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red_s[wv] = smax;
+        red_b[wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red_s[0];
+        int b = red_b[0];
+        for (int i = 1; i < kThreads / 64; ++i) {
+            m = fmax(m, red_s[i]);
+            b |= red_b[i];
+        }
+        unsigned long long bits = b ? 0x7FF8000000000000ULL
+                                    : (unsigned long long)__double_as_longlong(m);
+        atomicMax(&ctl->smax_bits[slot], bits);
+        if (b) atomicOr(&ctl->err, 1);
+    }
+}
+
+// ------------------------------------------------------------------------
+// The state-update kernel.  MODE: kXY / kYX (fused step), kX / kY (one sweep).
+// FINAL: this pass produces the end-of-step state (pointwise stage + CFL).
+template <class S, class R, int LIM, int MODE, bool FINAL>
+__global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
+    __shared__ R sWF[7][kThreads];
+    __shared__ R sH[6][kThreads];
+    Control *ctl = d.ctl;
+    if (ctl->skip) return;
+    const S lamx = (S)ctl->lam_x, lamy = (S)ctl->lam_y;
+    const R hlx = (R)ctl->hl_x, hly = (R)ctl->hl_y;
+    const int slot = (int)((ctl->step_exec + 1) & 1);
+
+    const Mix<S> ms = mix_of<S>(d);
+    const Mix<R> mr = mix_of<R>(d);
+    const S *src = (const S *)d.buf[src_idx];
+    S *dst = (S *)d.buf[src_idx ^ 1];
+    const long long plane = d.plane;
+    const int t = threadIdx.x;
+    const int x0 = blockIdx.x * kTileW;
+    const int col = x0 - kHalo + t;
+    const int gcol = map_idx(col, d.nx, d.bc_xlo, d.bc_xhi);
+    const bool out_col = (t >= kHalo) && (t < kThreads - kHalo) && (col < d.nx);
+    const int y0 = blockIdx.y * d.seg_h;
+    const int y1 = min(y0 + d.seg_h, d.ny);
+    const S zlo = (S)d.zlo, zhi = (S)d.zhi, idx = (S)d.idx, idy = (S)d.idy;
+
+    S smax = S(0);
+    int bad = 0;
+
+    auto load = [&](int k, S q[6]) {
+        const int gk = map_idx(k, d.ny, d.bc_ylo, d.bc_yhi);
+        const long long o = (long long)gk * d.pitch + gcol;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = src[c * plane + o];
+    };
+    auto store = [&](int k, S q[6]) {
+        if (FINAL) epilogue<S>(q, ms, zlo, zhi, idx, idy, smax, bad);
+        const long long o = (long long)k * d.pitch + col;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) dst[c * plane + o] = q[c];
+    };
+
+    if (MODE == kX) {
+        S qn[6];
+        load(y0, qn);
+        for (int k = y0; k < y1; ++k) {
+            S q[6], qo[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            if (k + 1 < y1) load(k + 1, qn);
+            x_row<S, R, LIM>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            if (out_col) store(k, qo);
+        }
+    } else {
+        YPipe<S, R, LIM> yp;
+        const int k0 = y0 - kHalo, k1 = y1 + kHalo;
+        S qn[6];
+        load(k0, qn);
+        for (int k = k0; k < k1; ++k) {
+            const int cnt = k - k0;
+            S q[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            if (k + 1 < k1) load(k + 1, qn);
+            if (MODE == kXY) {
+                S qs[6], qy[6], qo[6], qu[6];
+                x_row<S, R, LIM>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                to_yframe<S>(qs, qy);
+                if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
+                    to_yframe<S>(qo, qu);
+                    if (out_col) store(k - kHalo, qu);
+                }
+            } else {
+                S qy[6], qo[6], qu[6];
+                to_yframe<S>(q, qy);
+                const bool got = yp.push(cnt, qy, qo, lamy, hly, ms, mr);
+                to_yframe<S>(qo, qu);
+                if (MODE == kY) {
+                    if (got && out_col) store(k - kHalo, qu);
+                } else if (got) {  // kYX: x sweep of the row just finished in y
+                    S qx[6];
+                    x_row<S, R, LIM>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    if (out_col) store(k - kHalo, qx);
+                }
+            }
+        }
+    }
+    if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
+}
+
+// ------------------------------------------------------------------------
+// Small kernels around the step.
+
+// Time step of the step about to run (one thread).  dt_fixed > 0 overrides the
+// CFL bound; t_end > 0 shortens the last step to land on t_end and turns later
+// steps into no-ops.
+__global__ void dt_kernel(Control *ctl, double cfl, double dx, double dy, double dt_fixed,
+                          double t_end) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long long n = ctl->step;
+    if (ctl->err || (t_end > 0.0 && ctl->t >= t_end)) {
+        ctl->skip = 1;
+        return;
+    }
+    double dt;
+    if (dt_fixed > 0.0) {
+        dt = dt_fixed;
+    } else {
+        const double smax = __longlong_as_double((long long)ctl->smax_bits[n & 1]);
+        if (!(smax > 0.0) || !(smax <= 1.0e300)) {
+            ctl->err |= 1;
+            ctl->skip = 1;
+            return;
+        }
+        dt = cfl / smax;
+    }
+    const double t = ctl->t;
+    double tn;
+    if (t_end > 0.0 && t + dt >= t_end) {
+        dt = t_end - t;
+        tn = t_end;
+    } else {
+        tn = t + dt;
+    }
+    const double lx = dt / dx, ly = dt / dy;
+    ctl->dt = dt;
+    ctl->lam_x = lx;
+    ctl->lam_y = ly;
+    ctl->hl_x = 0.5 * lx;
+    ctl->hl_y = 0.5 * ly;
+    ctl->smax_bits[(n + 1) & 1] = 0ULL;
+    ctl->step_exec = n;
+    ctl->step = n + 1;
+    ctl->t = tn;
+    ctl->skip = 0;
+}
+
+__global__ void init_control_kernel(Control *ctl, double t, long long step) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ctl->t = t;
+    ctl->dt = 0.0;
+    ctl->lam_x = ctl->lam_y = ctl->hl_x = ctl->hl_y = 0.0;
+    ctl->smax_bits[0] = ctl->smax_bits[1] = 0ULL;
+    ctl->step = step;
+    ctl->step_exec = step;
+    ctl->skip = 0;
+    ctl->err = 0;
+}
+
+// Primitive planes (dense, FP64) -> conserved state (pitched, storage type).
+template <class S>
+__global__ void prim_to_cons_kernel(Desc d, int dst_idx, const double *prim) {
+    const long long N = (long long)d.nx * d.ny;
+    S *dst = (S *)d.buf[dst_idx];
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+         k += (long long)gridDim.x * blockDim.x) {
+        const double z = prim[k], r1 = prim[N + k], r2 = prim[2 * N + k];
+        const double u = prim[3 * N + k], v = prim[4 * N + k], p = prim[5 * N + k];
+        const double z2 = 1.0 - z;
+        const double a1 = z * r1, a2 = z2 * r2;
+        const double rho = a1 + a2;
+        const double xi = z * d.g1 + z2 * d.g2;
+        const double eta = z * d.h1 + z2 * d.h2;
+        const double E = (p * xi + eta) + 0.5 * (rho * (u * u + v * v));
+        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+        const long long o = (long long)j * d.pitch + i;
+        dst[o] = (S)a1;
+        dst[d.plane + o] = (S)a2;
+        dst[2 * d.plane + o] = (S)(rho * u);
+        dst[3 * d.plane + o] = (S)(rho * v);
+        dst[4 * d.plane + o] = (S)E;
+        dst[5 * d.plane + o] = (S)z;
+    }
+}
+
+template <class S>
+__global__ void cons_from_f64_kernel(Desc d, int dst_idx, const double *cons) {
+    const long long N = (long long)d.nx * d.ny;
+    S *dst = (S *)d.buf[dst_idx];
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+        const long long o = (long long)j * d.pitch + i;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) dst[c * d.plane + o] = (S)cons[c * N + k];
+    }
+}
+
+// CFL maximum of a state (no pointwise stage), into the slot of the current step.
+template <class S>
+__global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, int slot) {
+    const long long N = (long long)d.nx * d.ny;
+    const S *src = (const S *)d.buf[src_idx];
+    const Mix<S> ms = mix_of<S>(d);
+    const S idx = (S)d.idx, idy = (S)d.idy;
+    if (slot < 0) slot = (int)(d.ctl->step & 1);
+    S smax = S(0);
+    int bad = 0;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+        const long long o = (long long)j * d.pitch + i;
+        S q[6], w[6], r, rc2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
+        cons_to_prim<S>(ms, q, w, r, rc2);
+        const S c = Ar<S>::sqrt_(rc2 * r);
+        const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
+        if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S>::big())) bad = 1;
+        else smax = fmax(smax, s);
+    }
+    block_cfl_commit((double)smax, bad, d.ctl, slot);
+}
+
+// One field of the state as dense FP64 (conserved planes are widened,
+// derived fields use the closure in the storage type).
+template <class S>
+__global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
+    const long long N = (long long)d.nx * d.ny;
+    const S *src = (const S *)d.buf[src_idx];
+    const Mix<S> ms = mix_of<S>(d);
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+        const long long o = (long long)j * d.pitch + i;
+        if (field < 6) {
+            out[k] = (double)src[field * d.plane + o];
+            continue;
+        }
+        S q[6], w[6], r, rc2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
+        cons_to_prim<S>(ms, q, w, r, rc2);
+        double v;
+        switch (field) {
+            case 6: v = (double)(q[0] + q[1]); break;
+            case 7: v = (double)w[2]; break;
+            case 8: v = (double)w[3]; break;
+            case 9: v = (double)w[4]; break;
+            default: v = (double)Ar<S>::sqrt_(rc2 * r); break;
+        }
+        out[k] = v;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Launchers.
+static int grid_for(long long n) {
+    long long g = (n + kThreads - 1) / kThreads;
+    return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+hipError_t launch_init_control(const Desc &d, double t, long long step, hipStream_t st) {
+    hipLaunchKernelGGL(init_control_kernel, dim3(1), dim3(64), 0, st, d.ctl, t, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons(const Desc &d, int prec, int dst, const double *prim,
+                               hipStream_t st) {
+    const int g = grid_for((long long)d.nx * d.ny);
+    if (prec == kP32)
+        hipLaunchKernelGGL(prim_to_cons_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, dst,
+                           prim);
+    else
+        hipLaunchKernelGGL(prim_to_cons_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, dst,
+                           prim);
+    return hipGetLastError();
+}
+
+hipError_t launch_cons_from_f64(const Desc &d, int prec, int dst, const double *cons,
+                                hipStream_t st) {
+    const int g = grid_for((long long)d.nx * d.ny);
+    if (prec == kP32)
+        hipLaunchKernelGGL(cons_from_f64_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, dst,
+                           cons);
+    else
+        hipLaunchKernelGGL(cons_from_f64_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, dst,
+                           cons);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Desc &d, int prec, int src, hipStream_t st) {
+    const int g = grid_for((long long)d.nx * d.ny);
+    // slot -1: the slot read by the next step, i.e. the parity of the
+    // completed-step count held in the control block
+    if (prec == kP32)
+        hipLaunchKernelGGL(reduce_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, src, -1);
+    else
+        hipLaunchKernelGGL(reduce_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, src, -1);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(const Desc &d, double cfl, double dx, double dy, double dt_fixed,
+                     double t_end, hipStream_t st) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, st, d.ctl, cfl, dx, dy, dt_fixed, t_end);
+    return hipGetLastError();
+}
+
+template <class S, class R, int LIM>
+static void launch_step_t(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
+    const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
+    switch (mode) {
+        case kXY: hipLaunchKernelGGL((step_kernel<S, R, LIM, kXY, true>), grid, block, 0, st, d, src); break;
+        case kYX: hipLaunchKernelGGL((step_kernel<S, R, LIM, kYX, true>), grid, block, 0, st, d, src); break;
+        case kX:
+            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, LIM, kX, true>), grid, block, 0, st, d, src);
+            else hipLaunchKernelGGL((step_kernel<S, R, LIM, kX, false>), grid, block, 0, st, d, src);
+            break;
+        default:
+            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, LIM, kY, true>), grid, block, 0, st, d, src);
+            else hipLaunchKernelGGL((step_kernel<S, R, LIM, kY, false>), grid, block, 0, st, d, src);
+            break;
+    }
+}
+
+hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+                       hipStream_t st) {
+    if (prec == kP64) {
+        if (lim == 1) launch_step_t<double, double, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<double, double, 0>(d, mode, final_pass, src, st);
+    } else if (prec == kPMix) {
+        if (lim == 1) launch_step_t<double, float, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<double, float, 0>(d, mode, final_pass, src, st);
+    } else {
+        if (lim == 1) launch_step_t<float, float, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<float, float, 0>(d, mode, final_pass, src, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double *out,
+                             hipStream_t st) {
+    const int g = grid_for((long long)d.nx * d.ny);
+    if (prec == kP32)
+        hipLaunchKernelGGL(read_field_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, src,
+                           field, out);
+    else
+        hipLaunchKernelGGL(read_field_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, src,
+                           field, out);
+    return hipGetLastError();
+}
+
+}  // namespace meso

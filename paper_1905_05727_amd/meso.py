@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/meso.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``libmeso.so``; this module
+only converts arguments.  PyTorch supplies the device workspace (a uint8
+tensor) and the HIP stream.  If the library is missing, or no HIP device is
+present, construction raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmeso.so")
+
+MF_OK = 0
+STATUS = {0: "MF_OK", -1: "MF_E_INVALID_ARG", -2: "MF_E_OUT_OF_MEMORY",
+          -3: "MF_E_NONFINITE_STATE", -5: "MF_E_DEVICE", -6: "MF_E_NOT_READY", -7: "MF_E_BUSY"}
+PRECISION = {"fp64": 0, "fp32_fp64acc": 1, "mixed": 1, "fp32": 2}
+LIMITER = {"vanleer": 0, "minmod": 1}
+BC = {"transmissive": 0, "periodic": 1}
+FIELDS = {"z1rho1": 0, "z2rho2": 1, "rhou": 2, "rhov": 3, "rhoE": 4, "z1": 5,
+          "rho": 6, "u": 7, "v": 8, "p": 9, "c": 10}
+
+# every symbol the header declares
+EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conserved",
+           "mf_set_time", "mf_step", "mf_run_steps", "mf_run_to_time", "mf_sync",
+           "mf_read_field", "mf_read_conserved", "mf_get_time", "mf_enable_timing",
+           "mf_kernel_time", "mf_launch_info", "mf_destroy", "mf_status_str", "mf_version"]
+
+
+class MesoError(RuntimeError):
+    def __init__(self, call: str, status: int):
+        self.status = status
+        super().__init__(f"{call} failed: {STATUS.get(status, status)}")
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("bc_xlo", C.c_int32), ("bc_xhi", C.c_int32), ("bc_ylo", C.c_int32),
+                ("bc_yhi", C.c_int32)]
+
+
+class Material(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("p_inf", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("cfl", C.c_double), ("z_floor", C.c_double), ("limiter", C.c_int32),
+                ("precision", C.c_int32), ("fused", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmeso.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    D = C.POINTER(C.c_double)
+    I64 = C.POINTER(C.c_int64)
+    I32 = C.POINTER(C.c_int32)
+    sig = {
+        "mf_workspace_bytes": (C.c_size_t, [C.POINTER(Grid), C.c_int32]),
+        "mf_create": (C.c_int32, [C.POINTER(Grid), C.POINTER(Material), C.POINTER(Options),
+                                  P, C.c_size_t, P, C.POINTER(P)]),
+        "mf_set_primitive": (C.c_int32, [P, D]),
+        "mf_set_conserved": (C.c_int32, [P, D]),
+        "mf_set_time": (C.c_int32, [P, C.c_double, C.c_int64]),
+        "mf_step": (C.c_int32, [P, C.c_double]),
+        "mf_run_steps": (C.c_int32, [P, C.c_int64]),
+        "mf_run_to_time": (C.c_int32, [P, C.c_double, C.c_int64, I64]),
+        "mf_sync": (C.c_int32, [P]),
+        "mf_read_field": (C.c_int32, [P, C.c_int32, D, C.c_size_t]),
+        "mf_read_conserved": (C.c_int32, [P, D, C.c_size_t]),
+        "mf_get_time": (C.c_int32, [P, D, I64, D]),
+        "mf_enable_timing": (C.c_int32, [P, C.c_int32]),
+        "mf_kernel_time": (C.c_int32, [P, D, I64]),
+        "mf_launch_info": (C.c_int32, [P, I64, I32, I32, I32]),
+        "mf_destroy": (C.c_int32, [P]),
+        "mf_status_str": (C.c_char_p, [C.c_int32]),
+        "mf_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _chk(call: str, st: int) -> None:
+    if st != MF_OK:
+        raise MesoError(call, st)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_grid(nx, ny, dx, dy, bc=("transmissive",) * 4) -> Grid:
+    b = [BC[x] if isinstance(x, str) else int(x) for x in bc]
+    return Grid(int(nx), int(ny), float(dx), float(dy), *b)
+
+
+def workspace_bytes(nx, ny, dx=1.0, dy=1.0, precision="fp64", bc=("transmissive",) * 4) -> int:
+    g = make_grid(nx, ny, dx, dy, bc)
+    return int(load_library().mf_workspace_bytes(C.byref(g), PRECISION[precision]))
+
+
+class Solver:
+    """One shock/bubble solve resident on the current HIP device."""
+
+    def __init__(self, nx, ny, dx, dy, *, gamma1=1.4, pinf1=0.0, gamma2=4.4, pinf2=6.0e8,
+                 cfl=0.4, z_floor=1e-6, limiter="vanleer", precision="fp64", fused=True,
+                 bc=("transmissive",) * 4, workspace="torch", stream=None):
+        import torch
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the solver runs only on the GPU")
+        self.nx, self.ny = int(nx), int(ny)
+        self.precision = precision
+        self._lib = lib
+        self._grid = make_grid(nx, ny, dx, dy, bc)
+        mats = (Material * 2)(Material(gamma1, pinf1), Material(gamma2, pinf2))
+        opt = Options(float(cfl), float(z_floor), LIMITER[limiter], PRECISION[precision],
+                      1 if fused else 0, 0)
+        nbytes = int(lib.mf_workspace_bytes(C.byref(self._grid), PRECISION[precision]))
+        if nbytes == 0:
+            raise MesoError("mf_workspace_bytes", -1)
+        self._ws = None
+        ws_ptr = None
+        if workspace == "torch":
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            ws_ptr = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _chk("mf_create", lib.mf_create(C.byref(self._grid), mats, C.byref(opt),
+                                        ws_ptr, nbytes if ws_ptr else 0,
+                                        C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    # ---------------------------------------------------------------- state
+    @classmethod
+    def from_scenario(cls, sc, precision="fp64", fused=True, **kw):
+        s = cls(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1, gamma2=sc.gamma2,
+                pinf2=sc.pinf2, cfl=sc.cfl, z_floor=sc.zeps, limiter=sc.limiter,
+                precision=precision, fused=fused, bc=sc.bc, **kw)
+        s.set_primitive(sc.prim)
+        return s
+
+    def set_primitive(self, prim: np.ndarray) -> None:
+        prim = np.ascontiguousarray(prim, dtype=np.float64)
+        assert prim.size == 6 * self.nx * self.ny
+        _chk("mf_set_primitive", self._lib.mf_set_primitive(self._h, _dptr(prim)))
+
+    def set_conserved(self, U: np.ndarray) -> None:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.size == 6 * self.nx * self.ny
+        _chk("mf_set_conserved", self._lib.mf_set_conserved(self._h, _dptr(U)))
+
+    def set_time(self, t: float, step: int) -> None:
+        _chk("mf_set_time", self._lib.mf_set_time(self._h, float(t), int(step)))
+
+    # ------------------------------------------------------------ stepping
+    def step(self, dt: float = 0.0) -> None:
+        _chk("mf_step", self._lib.mf_step(self._h, float(dt)))
+
+    def run_steps(self, n: int) -> None:
+        _chk("mf_run_steps", self._lib.mf_run_steps(self._h, int(n)))
+
+    def run_to_time(self, t_end: float, max_steps: int = 10 ** 9) -> int:
+        taken = C.c_int64()
+        _chk("mf_run_to_time", self._lib.mf_run_to_time(self._h, float(t_end), int(max_steps),
+                                                         C.byref(taken)))
+        return taken.value
+
+    def sync(self) -> None:
+        _chk("mf_sync", self._lib.mf_sync(self._h))
+
+    # -------------------------------------------------------------- output
+    def read_field(self, name) -> np.ndarray:
+        f = FIELDS[name] if isinstance(name, str) else int(name)
+        out = np.empty((self.ny, self.nx), dtype=np.float64)
+        _chk("mf_read_field", self._lib.mf_read_field(self._h, f, _dptr(out), out.size))
+        return out
+
+    def read_conserved(self) -> np.ndarray:
+        out = np.empty((6, self.ny, self.nx), dtype=np.float64)
+        _chk("mf_read_conserved", self._lib.mf_read_conserved(self._h, _dptr(out), out.size))
+        return out
+
+    def time(self):
+        t = C.c_double()
+        n = C.c_int64()
+        dt = C.c_double()
+        _chk("mf_get_time", self._lib.mf_get_time(self._h, C.byref(t), C.byref(n), C.byref(dt)))
+        return t.value, n.value, dt.value
+
+    # -------------------------------------------------------------- timing
+    def enable_timing(self, on: bool = True) -> None:
+        _chk("mf_enable_timing", self._lib.mf_enable_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        _chk("mf_kernel_time", self._lib.mf_kernel_time(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def launch_info(self) -> dict:
+        wg = C.c_int64()
+        th, tw, tht = C.c_int32(), C.c_int32(), C.c_int32()
+        _chk("mf_launch_info", self._lib.mf_launch_info(self._h, C.byref(wg), C.byref(th),
+                                                         C.byref(tw), C.byref(tht)))
+        return dict(workgroups=wg.value, threads=th.value, tile_w=tw.value, tile_h=tht.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.mf_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

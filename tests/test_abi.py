@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports every declared symbol and validates its
+arguments on the host (no compute call needs a GPU here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1905_05727_amd import meso
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "meso.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_uses():
+    assert declared_functions() == sorted(meso.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = meso.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version():
+    lib = meso.load_library()
+    assert lib.mf_status_str(0) == b"ok"
+    assert lib.mf_status_str(-3) == b"non-finite or non-physical state"
+    assert lib.mf_version().startswith(b"meso")
+
+
+def test_workspace_bytes():
+    lib = meso.load_library()
+    for nx, ny in ((1, 1), (1000, 1), (1024, 512), (8192, 8192)):
+        pitch = (nx + 63) // 64 * 64
+        for prec, es in (("fp64", 8), ("fp32_fp64acc", 8), ("fp32", 4)):
+            state = (6 * pitch * ny * es + 255) // 256 * 256
+            assert meso.workspace_bytes(nx, ny, precision=prec) == 256 + 2 * state
+    g = meso.make_grid(0, 5, 1.0, 1.0)
+    assert lib.mf_workspace_bytes(C.byref(g), 0) == 0
+    g = meso.make_grid(5, 5, 1.0, 1.0)
+    assert lib.mf_workspace_bytes(C.byref(g), 7) == 0
+
+
+def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
+    lib = meso.load_library()
+    grid = grid or meso.make_grid(16, 8, 1e-3, 1e-3)
+    mats = mats or (meso.Material * 2)(meso.Material(1.4, 0.0), meso.Material(4.4, 6e8))
+    opt = opt or meso.Options(0.4, 1e-6, 0, 0, 1, 0)
+    h = C.c_void_p()
+    st = lib.mf_create(C.byref(grid), mats, C.byref(opt), ws, ws_bytes, None, C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("case", [
+    dict(grid=meso.make_grid(0, 8, 1e-3, 1e-3)),
+    dict(grid=meso.make_grid(16, 8, -1.0, 1e-3)),
+    dict(grid=meso.make_grid(16, 8, 1e-3, 1e-3, ("periodic", "transmissive", "transmissive",
+                                                  "transmissive"))),
+    dict(grid=meso.make_grid(16, 8, 1e-3, 1e-3, (3, 0, 0, 0))),
+    dict(mats=(meso.Material * 2)(meso.Material(1.0, 0.0), meso.Material(4.4, 6e8))),
+    dict(mats=(meso.Material * 2)(meso.Material(1.4, -1.0), meso.Material(4.4, 6e8))),
+    dict(opt=meso.Options(0.0, 1e-6, 0, 0, 1, 0)),
+    dict(opt=meso.Options(1.5, 1e-6, 0, 0, 1, 0)),
+    dict(opt=meso.Options(0.4, 0.6, 0, 0, 1, 0)),
+    dict(opt=meso.Options(0.4, 1e-6, 2, 0, 1, 0)),
+    dict(opt=meso.Options(0.4, 1e-6, 0, 3, 1, 0)),
+    dict(opt=meso.Options(0.4, 1e-6, 0, 0, 2, 0)),
+    dict(ws=0x1000, ws_bytes=10),          # workspace too small
+    dict(ws=0x1001, ws_bytes=1 << 40),     # misaligned workspace
+])
+def test_create_rejects_invalid_arguments(case):
+    st, h = _create(**case)
+    assert st == -1 and not h.value
+
+
+def test_null_handles_are_rejected():
+    lib = meso.load_library()
+    assert lib.mf_step(None, 0.0) == -1
+    assert lib.mf_run_steps(None, 1) == -1
+    assert lib.mf_sync(None) == -1
+    assert lib.mf_destroy(None) == -1
+    assert lib.mf_read_field(None, 0, None, 0) == -1
+    assert lib.mf_get_time(None, None, None, None) == -1
+    assert lib.mf_create(None, None, None, None, 0, None, None) == -1

@@ -1,0 +1,285 @@
+"""GPU path (through the C ABI) against the FP64 oracle.
+
+FP64 mode: element-by-element bitwise equality with the oracle (the tolerance
+stated for it is 1e-12 relative L1 per field; the kernels follow the same
+arithmetic contract, so the design target -- and the test -- is exact
+equality).  FP32 modes: relative L1 of density <= 1e-4 and of pressure <= 1e-3
+against FP64 after the fixed step count.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_05727_amd import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1905_05727_amd import meso  # noqa: E402
+
+LIM = {"vanleer": oracle.VANLEER, "minmod": oracle.MINMOD}
+BCO = {"transmissive": oracle.TRANSMISSIVE, "periodic": oracle.PERIODIC}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_of(sc, limiter=None):
+    bc = [BCO[b] for b in sc.bc]
+    P = oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1,
+                       gamma2=sc.gamma2, pinf2=sc.pinf2, cfl=sc.cfl, zeps=sc.zeps,
+                       limiter=LIM[limiter or sc.limiter], bc_xlo=bc[0], bc_xhi=bc[1],
+                       bc_ylo=bc[2], bc_yhi=bc[3])
+    o = oracle.Oracle(P)
+    o.set_primitive(sc.prim)
+    return o
+
+
+def assert_bitwise(U, V, what):
+    if not np.array_equal(U, V):
+        d = np.abs(U - V)
+        k = np.unravel_index(np.argmax(d), d.shape)
+        raise AssertionError(f"{what}: {np.count_nonzero(d)} values differ, max {d.max()} at {k}")
+
+
+def rel_l1(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def bubble(nx, ny, periodic=False, limiter="vanleer"):
+    sc = S.single_bubble(nx=nx, ny=ny, radius=min(nx, ny) / 5, centre=(nx * 0.55, ny / 2),
+                         shock_x=nx * 0.3)
+    sc.limiter = limiter
+    if periodic:
+        sc.bc = ("periodic",) * 4
+    return sc
+
+
+# ----------------------------------------------------------------- FP64 ----
+@pytest.mark.parametrize("fused", [True, False])
+def test_fp64_shock_tube_bitwise(fused):
+    sc = S.shock_tube_1d()
+    say(f"case: shock tube 1000x1, run to {sc.t_end}, fused={fused}")
+    with meso.Solver.from_scenario(sc, precision="fp64", fused=fused) as s:
+        taken = s.run_to_time(sc.t_end)
+        U = s.read_conserved()
+        t, n, dt = s.time()
+    o = oracle_of(sc)
+    no = o.run(10 ** 6, t_end=sc.t_end)
+    assert taken == no and n == no and t == o.t == sc.t_end
+    assert dt == o.last_dt
+    assert_bitwise(U, o.U, "shock tube")
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod"])
+@pytest.mark.parametrize("shape", [(300, 200), (253, 37), (5, 300)])
+def test_fp64_bubble_bitwise(shape, limiter, fused):
+    nx, ny = shape
+    sc = bubble(nx, ny, limiter=limiter)
+    say(f"case: bubble {nx}x{ny} {limiter} fused={fused}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64", fused=fused) as s:
+        done = 0
+        for upto in (1, 2, 3, 30):
+            s.run_steps(upto - done)
+            o.run(upto - done)
+            done = upto
+            t, n, dt = s.time()
+            assert n == o.step and t == o.t and dt == o.last_dt, (upto, t, o.t)
+            assert_bitwise(s.read_conserved(), o.U, f"after {upto} steps")
+
+
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod"])
+def test_fp64_periodic_bitwise(limiter):
+    sc = bubble(270, 70, periodic=True, limiter=limiter)
+    say(f"case: periodic bubble 270x70 {limiter}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(25)
+        o.run(25)
+        assert_bitwise(s.read_conserved(), o.U, "periodic")
+
+
+def test_fp64_single_bubble_full_size_bitwise():
+    sc = S.single_bubble()
+    say("case: single bubble 1024x512 (full size), 12 steps")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        say("launch", s.launch_info())
+        s.run_steps(12)
+        o.run(12)
+        assert_bitwise(s.read_conserved(), o.U, "1024x512")
+
+
+def test_fp64_explicit_dt_and_resume():
+    """Explicit dt steps, checkpoint (read conserved + time) and resume in a new
+    solver reproduce an uninterrupted run bit for bit."""
+    sc = bubble(200, 90)
+    say("case: explicit dt + checkpoint/resume 200x90")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.step(1.0e-9)
+        o.step_dt(1.0e-9)
+        assert_bitwise(s.read_conserved(), o.U, "explicit dt")
+        s.run_steps(6)
+        U6 = s.read_conserved()
+        t6, n6, _ = s.time()
+        s.run_steps(7)
+        U13 = s.read_conserved()
+    with meso.Solver(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl) as r:
+        r.set_conserved(U6)
+        r.set_time(t6, n6)
+        r.run_steps(7)
+        assert_bitwise(r.read_conserved(), U13, "resume")
+    o.run(13)
+    assert_bitwise(U13, o.U, "explicit dt then CFL")
+
+
+def test_fp64_run_to_time_lands_on_end_time():
+    sc = bubble(128, 64)
+    say("case: run_to_time 128x64")
+    o = oracle_of(sc)
+    t_end = 2.5e-8
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        k = s.run_to_time(t_end)
+        t, n, _ = s.time()
+        assert t == t_end and k == n
+        assert s.run_to_time(t_end) == 0
+        no = o.run(10 ** 6, t_end=t_end)
+        assert no == k
+        assert_bitwise(s.read_conserved(), o.U, "run_to_time")
+
+
+@pytest.mark.parametrize("start", [3, 4])
+def test_fp64_roofline_8192_sampled(start):
+    """Full 8192^2 roofline workload in the benchmark's launch configuration:
+    after `start` steps, one more step (x-y order if start is even, y-x if odd)
+    is checked against the oracle on sampled cells (interior, edges, corners,
+    strip and segment seams, the ragged last strip), and the time step against
+    the oracle's full-grid CFL maximum."""
+    sc = S.roofline_8192()
+    n = sc.nx
+    say(f"case: roofline 8192x8192 sampled, start={start}")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        info = s.launch_info()
+        say("launch", info)
+        s.run_steps(start)
+        U0 = s.read_conserved()
+        t0, n0, _ = s.time()
+        s.run_steps(1)
+        U1 = s.read_conserved()
+        t1, n1, dt = s.time()
+    o = oracle_of(sc)
+    o.U[...] = U0
+    o.t, o.step = t0, n0
+    dto, tno = o.cfl_dt()
+    assert dt == dto and t1 == tno
+    rng = np.random.default_rng(start)
+    ii = list(rng.integers(0, n, 3000))
+    jj = list(rng.integers(0, n, 3000))
+    tw, th = info["tile_w"], info["tile_h"]
+    special_i = [0, 1, 2, n - 3, n - 2, n - 1, tw - 1, tw, tw + 1, 32 * tw - 1, 32 * tw,
+                 32 * tw + 1]
+    special_j = [0, 1, 2, n - 3, n - 2, n - 1, th - 1, th, th + 1, 2 * th - 1, 2 * th]
+    for a in special_i:
+        for b in special_j:
+            ii.append(a)
+            jj.append(b)
+    cells = np.array(jj, dtype=np.int64) * n + np.array(ii, dtype=np.int64)
+    exp = o.step_cells(U0, n0, dto, cells)
+    got = U1.reshape(6, -1)[:, cells]
+    assert_bitwise(got, exp, "sampled 8192^2")
+
+
+# ------------------------------------------------------------ FP32 modes ----
+def test_reduced_precision_modes_within_tolerance():
+    """Single bubble 1024x512, 2000 steps: FP32-bulk/FP64-accumulate and pure
+    FP32 against FP64 (relative L1, density <= 1e-4, pressure <= 1e-3)."""
+    sc = S.single_bubble()
+    say("case: single bubble 1024x512, 2000 steps, three precisions")
+    res = {}
+    for prec in ("fp64", "fp32_fp64acc", "fp32"):
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            s.run_steps(2000)
+            res[prec] = {k: s.read_field(k) for k in ("rho", "p", "u", "z1")}
+            say(prec, "t =", s.time()[0])
+    for prec in ("fp32_fp64acc", "fp32"):
+        e_rho = rel_l1(res[prec]["rho"], res["fp64"]["rho"])
+        e_p = rel_l1(res[prec]["p"], res["fp64"]["p"])
+        say(f"{prec}: rel L1 rho {e_rho:.3e}  p {e_p:.3e}")
+        assert e_rho <= 1e-4 and e_p <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32_fp64acc", "fp32"])
+def test_reduced_precision_against_oracle(prec):
+    sc = bubble(256, 128)
+    say(f"case: bubble 256x128 400 steps {prec} vs oracle")
+    o = oracle_of(sc)
+    o.run(400)
+    ref = o.primitive()
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(400)
+        rho, p = s.read_field("rho"), s.read_field("p")
+    assert rel_l1(rho, ref["rho"]) <= 1e-4
+    assert rel_l1(p, ref["p"]) <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_fused_equals_unfused(prec):
+    sc = bubble(300, 140)
+    say(f"case: fused vs unfused 300x140 {prec}")
+    out = []
+    for fused in (True, False):
+        with meso.Solver.from_scenario(sc, precision=prec, fused=fused) as s:
+            s.run_steps(21)
+            out.append(s.read_conserved())
+    assert_bitwise(out[0], out[1], "fused vs unfused")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_conservation_and_symmetry_on_gpu(prec):
+    sc = bubble(256, 96, periodic=True)
+    say(f"case: periodic conservation 256x96 {prec}")
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        U0 = s.read_conserved()
+        s.run_steps(150)
+        U1 = s.read_conserved()
+    s0, s1 = U0[:5].sum(axis=(1, 2)), U1[:5].sum(axis=(1, 2))
+    scale = np.abs(U0[:5]).sum(axis=(1, 2))
+    tol = 1e-13 if prec != "fp32" else 1e-6
+    assert np.all(np.abs(s1 - s0) <= tol * 150 * scale), (s1 - s0) / scale
+    if prec == "fp64":
+        flip = U1[:, ::-1, :] * np.array([1, 1, 1, -1, 1, 1.0])[:, None, None]
+        assert np.array_equal(U1, flip)
+
+
+# ------------------------------------------------------------ error paths ----
+def test_nonfinite_state_is_reported():
+    """A NaN or a negative density set from the host is latched on the device
+    and reported by the next synchronising call; later steps do nothing."""
+    sc = bubble(64, 32)
+    for bad in ("nan", "negrho"):
+        say(f"case: bad state {bad}")
+        prim = sc.prim.copy()
+        if bad == "nan":
+            prim[5, 10, 10] = np.nan
+        else:
+            prim[2, 10, 10] = -5.0
+        with meso.Solver(sc.nx, sc.ny, sc.dx, sc.dy) as s:
+            s.set_primitive(prim)
+            with pytest.raises(meso.MesoError) as ei:
+                s.sync()
+            assert ei.value.status == -3
+            s.run_steps(3)
+            with pytest.raises(meso.MesoError):
+                s.sync()
+            # a good state clears the error
+            s.set_primitive(sc.prim)
+            s.run_steps(2)
+            s.sync()
+            assert s.time()[1] == 2
