@@ -117,10 +117,11 @@ def _paint_bubble(w: np.ndarray, xc: float, yc: float, R: float) -> None:
     fall below 1e-13."""
     ny, nx = w.shape
     h = R + 16.0
-    i0 = max(0, int(math.floor(xc - h)))
-    i1 = min(nx, int(math.ceil(xc + h)) + 1)
-    j0 = max(0, int(math.floor(yc - h)))
-    j1 = min(ny, int(math.ceil(yc + h)) + 1)
+    # cells whose centre lies within h of the centre: a window symmetric about it
+    i0 = max(0, int(math.ceil(xc - h - 0.5)))
+    i1 = min(nx, int(math.floor(xc + h - 0.5)) + 1)
+    j0 = max(0, int(math.ceil(yc - h - 0.5)))
+    j1 = min(ny, int(math.floor(yc + h - 0.5)) + 1)
     if i0 >= i1 or j0 >= j1:
         return
     xs = (np.arange(i0, i1, dtype=np.float64) + 0.5) - xc

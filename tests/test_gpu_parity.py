@@ -251,6 +251,7 @@ def test_conservation_and_symmetry_on_gpu(prec):
         U1 = s.read_conserved()
     s0, s1 = U0[:5].sum(axis=(1, 2)), U1[:5].sum(axis=(1, 2))
     scale = np.abs(U0[:5]).sum(axis=(1, 2))
+    scale[2] = scale[3] = np.abs(U0[2]).sum() + np.abs(U0[3]).sum()   # momentum scale
     tol = 1e-13 if prec != "fp32" else 1e-6
     assert np.all(np.abs(s1 - s0) <= tol * 150 * scale), (s1 - s0) / scale
     if prec == "fp64":

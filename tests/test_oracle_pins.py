@@ -416,6 +416,14 @@ def test_mirror_symmetry_bitwise():
     assert np.any(U[3] != 0)
 
 
+def test_mirror_symmetry_periodic_bitwise():
+    o = bubble_scene(80, 48, periodic=True)
+    assert np.array_equal(o.U, o.U[:, ::-1, :] * np.array([1, 1, 1, -1, 1, 1.0])[:, None, None])
+    o.run(60)
+    sign = np.array([1, 1, 1, -1, 1, 1.0])[:, None, None]
+    assert np.array_equal(o.U, o.U[:, ::-1, :] * sign)
+
+
 def test_y_uniform_2d_equals_1d():
     sc = S.shock_tube_1d(nx=300, sharp=False)
     o1 = oracle.Oracle(prob(300, 1, dx=sc.dx, cfl=0.5, limiter=oracle.MINMOD))
