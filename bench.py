@@ -80,6 +80,29 @@ def run_mode(sc, prec, steps, warmup, ref=None):
     return out
 
 
+def copy_bandwidth(gib: float = 2.0, reps: int = 5):
+    """Plain device-to-device copy of a known size: the achievable HBM ceiling
+    and the reference against which rocprofv3's FETCH_SIZE / WRITE_SIZE are
+    scaled (read + write of `gib` GiB per launch)."""
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * n * 8, "ms": ms, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(sc, nsteps):
     import oracle
     o = oracle.Oracle(oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl))
@@ -142,6 +165,9 @@ def main():
                                                  / np.abs(ref["fields"][k]).sum())
         mode_out[m] = d
 
+    cp = copy_bandwidth()
+    log(f"device copy: {cp['GBs']:.0f} GB/s ({cp['bytes_per_launch'] / 2 ** 30:.1f} GiB moved "
+        f"per launch)")
     head = "fp64" if "fp64" in res else modes[0]
     h = mode_out[head]
     r = res[head]
@@ -167,7 +193,8 @@ def main():
                      "unit": "GB/s", "frac": h["roofline_frac"],
                      "traffic": traffic_from_profiles(head),
                      "kernel": "step_kernel (fused x/y sweep)",
-                     "bytes_per_cell": BYTES_PER_CELL[head]},
+                     "bytes_per_cell": BYTES_PER_CELL[head],
+                     "copy_kernel_GBs": cp["GBs"]},
         "modes": mode_out,
     }
     if not args.no_cpu_baseline:

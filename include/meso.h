@@ -181,6 +181,94 @@ int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches);
 int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int32_t *tile_w,
                        int32_t *tile_h);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching server: many independent solves of different grid
+ * sizes share one device.  Each admitted solve holds a slot and a block of a
+ * fixed device arena (its state copies, control block and a read-back area);
+ * every tick advances all admitted solves by one CFL step with ONE batched
+ * state-update launch over a table of (solve, strip, segment) tiles.  Solves
+ * that finish are read back on a second stream while the others keep running;
+ * their slot and memory are then reused by queued requests (first come, first
+ * served).  Each solve's arithmetic is exactly that of a lone mf_solver with
+ * the same options, so its result does not depend on what it shares the
+ * device with.
+ * ------------------------------------------------------------------------ */
+
+typedef struct mf_server mf_server;
+
+/* hbm_budget: bytes of device memory the server may hold for solves (one
+ *   arena allocated at creation); max_slots: most solves on the device at
+ *   once; precision and limiter: shared by all requests; max_inflight: ticks
+ *   enqueued ahead of the device before mf_server_tick waits (>= 1). */
+typedef struct {
+    size_t hbm_budget;
+    int32_t max_slots;
+    int32_t precision;
+    int32_t limiter;
+    int32_t max_inflight;
+} mf_server_config;
+
+/* Request states reported by mf_server_poll. */
+#define MF_REQ_QUEUED  0
+#define MF_REQ_RUNNING 1
+#define MF_REQ_DONE    2
+#define MF_REQ_FAILED  3
+
+/* Aggregate counters of a server. */
+typedef struct {
+    int64_t ticks;            /* batched steps launched                      */
+    int64_t cell_updates;     /* sum over ticks of the cells advanced        */
+    int64_t completed;        /* requests finished (done or failed)          */
+    int64_t peak_bytes;       /* largest arena use so far                    */
+    int64_t bytes_in_use;     /* arena use now                               */
+    int32_t active;           /* solves advancing                            */
+    int32_t queued;           /* requests waiting for admission              */
+    int32_t draining;         /* finished solves being read back             */
+    int32_t reserved;
+} mf_server_stats;
+
+/* Device bytes one request of this grid needs inside the arena. */
+size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision);
+
+/* Create a server on the current device.  hip_stream: stream for the batched
+ * steps (NULL: the server creates its own non-blocking stream); the read-back
+ * stream is always the server's own.  Errors: MF_E_INVALID_ARG,
+ * MF_E_OUT_OF_MEMORY (arena allocation), MF_E_DEVICE. */
+int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_server **out);
+
+/* Queue one solve: grid, materials (gas, liquid), options (cfl, z_floor;
+ * limiter and precision must equal the server's; fused is ignored), host
+ * primitive planes (6*nx*ny doubles, copied during the call) and the number
+ * of CFL steps to take (>= 1).  *ticket receives the request id.
+ * MF_E_OUT_OF_MEMORY if the request can never fit in the budget. */
+int32_t mf_server_submit(mf_server *srv, const mf_grid *grid, const mf_material mat[2],
+                         const mf_options *opt, const double *prim, int64_t nsteps,
+                         uint64_t *ticket);
+
+/* One scheduling round: collect finished read-backs, admit queued requests
+ * while a slot and arena memory are free, and enqueue one batched step of all
+ * admitted solves.  Waits only when max_inflight ticks are already queued on
+ * the device.  *active / *queued (may be NULL) receive the counts after it. */
+int32_t mf_server_tick(mf_server *srv, int32_t *active, int32_t *queued);
+
+/* State of a request (MF_REQ_*); MF_E_INVALID_ARG for an unknown ticket. */
+int32_t mf_server_poll(mf_server *srv, uint64_t ticket, int32_t *state);
+
+/* Copy a finished request's 6 conserved planes (6*nx*ny doubles), its final
+ * time and step count, and forget the request.  MF_E_NOT_READY while it runs,
+ * MF_E_NONFINITE_STATE if its state became non-physical (the ticket is then
+ * released as well). */
+int32_t mf_server_result(mf_server *srv, uint64_t ticket, double *out_cons, size_t count,
+                         double *t, int64_t *steps);
+
+/* Tick until every submitted request is finished and read back. */
+int32_t mf_server_drain(mf_server *srv);
+
+int32_t mf_server_get_stats(mf_server *srv, mf_server_stats *st);
+
+/* Wait for the device, release every resource; pending tickets are lost. */
+int32_t mf_server_destroy(mf_server *srv);
+
 /* Release the solver (and the workspace if the library allocated it).
  * Synchronises its stream first. */
 int32_t mf_destroy(mf_solver *s);

@@ -13,7 +13,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmeso.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("meso_kernels.hip", "meso_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("meso_kernels.hip", "meso_api.hip", "meso_server.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 

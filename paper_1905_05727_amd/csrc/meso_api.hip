@@ -17,13 +17,9 @@
 using meso::Control;
 using meso::Desc;
 
-namespace {
+namespace meso {
 
-constexpr size_t kAlign = 256;
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-bool grid_ok(const mf_grid *g) {
+bool valid_grid(const mf_grid *g) {
     if (!g) return false;
     if (g->nx < 1 || g->ny < 1) return false;
     if (!(g->dx > 0.0) || !(g->dy > 0.0) || !isfinite(g->dx) || !isfinite(g->dy)) return false;
@@ -36,13 +32,75 @@ bool grid_ok(const mf_grid *g) {
     return true;
 }
 
-size_t elem_size(int32_t prec) { return prec == MF_FP32 ? 4 : 8; }
-
-int pitch_of(int nx) { return (int)round_up((size_t)nx, 64); }
-
-size_t state_bytes(const mf_grid *g, int32_t prec) {
-    return round_up((size_t)6 * pitch_of(g->nx) * (size_t)g->ny * elem_size(prec), kAlign);
+bool valid_materials(const mf_material *mat) {
+    if (!mat) return false;
+    for (int k = 0; k < 2; ++k)
+        if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
+            !isfinite(mat[k].p_inf))
+            return false;
+    return true;
 }
+
+bool valid_scheme(const mf_options *opt) {
+    if (!opt) return false;
+    if (!(opt->cfl > 0.0) || !(opt->cfl <= 1.0)) return false;
+    if (!(opt->z_floor >= 0.0) || !(opt->z_floor < 0.5)) return false;
+    if (opt->limiter != MF_LIM_VANLEER && opt->limiter != MF_LIM_MINMOD) return false;
+    if (opt->precision < MF_FP64 || opt->precision > MF_FP32) return false;
+    return true;
+}
+
+size_t state_bytes(const mf_grid *g, int prec) {
+    const size_t es = prec == MF_FP32 ? 4 : 8;
+    return round_up((size_t)6 * pitch_of(g->nx) * (size_t)g->ny * es, kAlign);
+}
+
+int choose_seg_h(int nstrips, int ny) {
+    const char *env = getenv("MESO_SEG_H");
+    if (env) {
+        const int v = atoi(env);
+        if (v >= 1) return v;
+    }
+    int h = 128;
+    while (h > 16 && (long long)nstrips * ((ny + h - 1) / h) < 512) h >>= 1;
+    return h;
+}
+
+void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,
+               char *base, int seg_h) {
+    d.ctl = (Control *)base;
+    d.buf[0] = base + kAlign;
+    d.buf[1] = base + kAlign + state_bytes(g, opt->precision);
+    d.nx = g->nx;
+    d.ny = g->ny;
+    d.pitch = pitch_of(g->nx);
+    d.plane = (long long)d.pitch * g->ny;
+    d.bc_xlo = g->bc_xlo;
+    d.bc_xhi = g->bc_xhi;
+    d.bc_ylo = g->bc_ylo;
+    d.bc_yhi = g->bc_yhi;
+    d.nstrips = (g->nx + kTileW - 1) / kTileW;
+    d.seg_h = seg_h > 0 ? seg_h : choose_seg_h(d.nstrips, g->ny);
+    d.nsegs = (g->ny + d.seg_h - 1) / d.seg_h;
+    d.dx = g->dx;
+    d.dy = g->dy;
+    d.cfl = opt->cfl;
+    d.idx = 1.0 / g->dx;
+    d.idy = 1.0 / g->dy;
+    d.zlo = opt->z_floor;
+    d.zhi = 1.0 - opt->z_floor;
+    d.g1 = 1.0 / (mat[0].gamma - 1.0);
+    d.g2 = 1.0 / (mat[1].gamma - 1.0);
+    d.h1 = (mat[0].gamma * mat[0].p_inf) * d.g1;
+    d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
+}
+
+}  // namespace meso
+
+namespace {
+
+using meso::kAlign;
+using meso::state_bytes;
 
 struct EventPair {
     hipEvent_t a, b;
@@ -127,23 +185,12 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
     return MF_OK;
 }
 
-int choose_seg_h(int nstrips, int ny) {
-    const char *env = getenv("MESO_SEG_H");
-    if (env) {
-        const int v = atoi(env);
-        if (v >= 1) return v;
-    }
-    int h = 128;
-    while (h > 16 && (long long)nstrips * ((ny + h - 1) / h) < 512) h >>= 1;
-    return h;
-}
-
 }  // namespace
 
 extern "C" {
 
 size_t mf_workspace_bytes(const mf_grid *grid, int32_t precision) {
-    if (!grid_ok(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
+    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
     return kAlign + 2 * state_bytes(grid, precision);
 }
 
@@ -151,15 +198,8 @@ int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_option
                   void *dev_workspace, size_t ws_bytes, void *hip_stream, mf_solver **out) {
     if (!out) return MF_E_INVALID_ARG;
     *out = nullptr;
-    if (!grid_ok(grid) || !mat || !opt) return MF_E_INVALID_ARG;
-    for (int k = 0; k < 2; ++k)
-        if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
-            !isfinite(mat[k].p_inf))
-            return MF_E_INVALID_ARG;
-    if (!(opt->cfl > 0.0) || !(opt->cfl <= 1.0)) return MF_E_INVALID_ARG;
-    if (!(opt->z_floor >= 0.0) || !(opt->z_floor < 0.5)) return MF_E_INVALID_ARG;
-    if (opt->limiter != MF_LIM_VANLEER && opt->limiter != MF_LIM_MINMOD) return MF_E_INVALID_ARG;
-    if (opt->precision < MF_FP64 || opt->precision > MF_FP32) return MF_E_INVALID_ARG;
+    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt))
+        return MF_E_INVALID_ARG;
     if (opt->fused != 0 && opt->fused != 1) return MF_E_INVALID_ARG;
     const size_t need = mf_workspace_bytes(grid, opt->precision);
     if (dev_workspace && (ws_bytes < need || ((uintptr_t)dev_workspace % kAlign) != 0))
@@ -185,30 +225,8 @@ int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_option
     } else {
         s->ws = dev_workspace;
     }
-    char *base = (char *)s->ws;
     Desc &d = s->d;
-    d.ctl = (Control *)base;
-    d.buf[0] = base + kAlign;
-    d.buf[1] = base + kAlign + state_bytes(grid, opt->precision);
-    d.nx = grid->nx;
-    d.ny = grid->ny;
-    d.pitch = pitch_of(grid->nx);
-    d.plane = (long long)d.pitch * grid->ny;
-    d.bc_xlo = grid->bc_xlo;
-    d.bc_xhi = grid->bc_xhi;
-    d.bc_ylo = grid->bc_ylo;
-    d.bc_yhi = grid->bc_yhi;
-    d.nstrips = (grid->nx + meso::kTileW - 1) / meso::kTileW;
-    d.seg_h = choose_seg_h(d.nstrips, grid->ny);
-    d.nsegs = (grid->ny + d.seg_h - 1) / d.seg_h;
-    d.idx = 1.0 / grid->dx;
-    d.idy = 1.0 / grid->dy;
-    d.zlo = opt->z_floor;
-    d.zhi = 1.0 - opt->z_floor;
-    d.g1 = 1.0 / (mat[0].gamma - 1.0);
-    d.g2 = 1.0 / (mat[1].gamma - 1.0);
-    d.h1 = (mat[0].gamma * mat[0].p_inf) * d.g1;
-    d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
+    meso::fill_desc(d, grid, mat, opt, (char *)s->ws, 0);
 
     hipError_t e = hipMemsetAsync(s->ws, 0, need, s->stream);
     if (e == hipSuccess) e = meso::launch_init_control(d, 0.0, 0, s->stream);

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "meso.h"
 
 namespace meso {
 
@@ -44,10 +47,26 @@ struct Desc {
     long long plane;         // elements per plane
     int bc_xlo, bc_xhi, bc_ylo, bc_yhi;
     int nstrips, nsegs;
+    double dx, dy, cfl;      // cell sizes and CFL number (used by the batched dt kernel)
     double idx, idy;         // 1/dx, 1/dy
     double zlo, zhi;         // eps, 1 - eps of the pointwise stage
     double g1, g2, h1, h2;   // mixture constants 1/(gamma-1), gamma pinf/(gamma-1)
 };
+
+// Host helpers shared by the solver and the server (meso_api.hip).
+constexpr size_t kAlign = 256;
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int pitch_of(int nx) { return (int)round_up((size_t)nx, 64); }
+bool valid_grid(const mf_grid *g);
+bool valid_materials(const mf_material *mat);
+bool valid_scheme(const mf_options *opt);
+// bytes of one pitched state copy (6 planes), 256-byte rounded
+size_t state_bytes(const mf_grid *g, int prec);
+int choose_seg_h(int nstrips, int ny);
+// Fill a descriptor for a solve whose workspace (control block + two state
+// copies) starts at base.
+void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,
+               char *base, int seg_h);
 
 // Launchers (meso_kernels.hip).  All enqueue on `st` and return the launch
 // status.  `prec` is kP64 / kPMix / kP32, `lim` the limiter id.
@@ -63,5 +82,10 @@ hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pas
                        hipStream_t st);
 hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double *out,
                              hipStream_t st);
+// Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
+// into descs, strip, segment, unused).
+hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);
+hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
+                               int lim, hipStream_t st);
 
 }  // namespace meso

@@ -35,15 +35,29 @@
 namespace meso {
 
 // ------------------------------------------------------------------------
-// Arithmetic helpers: exact IEEE for double, hardware approximations for float.
-template <class T> struct Ar;
-template <> struct Ar<double> {
+// Arithmetic policies.  Ar<double, false>: IEEE division and square root (the
+// FP64 mode, bit-compatible with the arithmetic contract).  Ar<double, true>:
+// hardware reciprocal refined by one Newton step and the hardware square
+// root (the FP64 closure of the FP32-bulk mode).  Ar<float, *>: hardware
+// reciprocal and square root.
+template <class T, bool FAST> struct Ar;
+template <> struct Ar<double, false> {
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
     static __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
     static __device__ __forceinline__ double big() { return 1.0e300; }
 };
-template <> struct Ar<float> {
+template <> struct Ar<double, true> {
+    static __device__ __forceinline__ double rcp(double a) {
+        const double r = __builtin_amdgcn_rcp(a);
+        const double e = __builtin_fma(-a, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
+    static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
+    static __device__ __forceinline__ double sqrt_(double a) { return __builtin_amdgcn_sqrt(a); }
+    static __device__ __forceinline__ double big() { return 1.0e300; }
+};
+template <bool FAST> struct Ar<float, FAST> {
     static __device__ __forceinline__ float div(float a, float b) {
         return a * __builtin_amdgcn_rcpf(b);
     }
@@ -72,11 +86,11 @@ __device__ __forceinline__ int map_idx(int i, int n, int bc_lo, int bc_hi) {
 // ------------------------------------------------------------------------
 // Closure (Sec. 2.1): sweep-frame conserved q = (a1, a2, mn, mt, E, z) to
 // primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2.
-template <class S>
+template <class S, bool FAST>
 __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[6], S &r,
                                              S &rc2) {
     const S rho = q[0] + q[1];
-    r = Ar<S>::rcp(rho);
+    r = Ar<S, FAST>::rcp(rho);
     const S un = q[2] * r;
     const S ut = q[3] * r;
     const S ke = S(0.5) * (q[2] * un + q[3] * ut);
@@ -85,32 +99,32 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[
     const S z2 = S(1) - z;
     const S xi = z * m.g1 + z2 * m.g2;
     const S eta = z * m.h1 + z2 * m.h2;
-    const S ixi = Ar<S>::rcp(xi);
+    const S ixi = Ar<S, FAST>::rcp(xi);
     const S p = (rhoe - eta) * ixi;
     rc2 = (p * (S(1) + xi) + eta) * ixi;
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
 }
 
 // Slope limiter (Sec. 3): a backward, b forward difference.
-template <class R, int LIM>
+template <class R, bool FAST, int LIM>
 __device__ __forceinline__ R limit(R a, R b) {
     const R ab = a * b;
     R s;
     if (LIM == 1) {
         s = (a > R(0)) ? fmin(a, b) : fmax(a, b);
     } else {
-        s = Ar<R>::div(ab + ab, a + b);
+        s = Ar<R, FAST>::div(ab + ab, a + b);
     }
     return (ab > R(0)) ? s : R(0);
 }
 
 // MUSCL reconstruction and Hancock half step in primitive variables.
-template <class R, int LIM>
+template <class R, bool FAST, int LIM>
 __device__ __forceinline__ void face_states(const R wm[6], const R w0[6], const R wp[6], R r,
                                             R rc2, R hl, R wl[6], R wh[6]) {
     R d[6], s[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) d[c] = limit<R, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
+    for (int c = 0; c < 6; ++c) d[c] = limit<R, FAST, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
     const R un = w0[2];
     s[0] = hl * (un * d[0] + w0[0] * d[2]);
     s[1] = hl * (un * d[1] + w0[1] * d[2]);
@@ -130,14 +144,14 @@ template <class R> struct Side {
     R U[5], F[5];
 };
 
-template <class R>
+template <class R, bool FAST>
 __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R> &s, R &c) {
     const R rho = w[0] + w[1];
     const R un = w[2], ut = w[3], p = w[4], z = w[5];
     const R z2 = R(1) - z;
     const R xi = z * m.g1 + z2 * m.g2;
     const R eta = z * m.h1 + z2 * m.h2;
-    c = Ar<R>::sqrt_(Ar<R>::div(p * (R(1) + xi) + eta, xi * rho));
+    c = Ar<R, FAST>::sqrt_(Ar<R, FAST>::div(p * (R(1) + xi) + eta, xi * rho));
     const R E = (p * xi + eta) + R(0.5) * (rho * (un * un + ut * ut));
     const R mn = rho * un;
     s.rho = rho; s.un = un; s.ut = ut; s.p = p; s.z = z; s.E = E;
@@ -149,16 +163,16 @@ __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R>
     s.F[4] = (E + p) * un;
 }
 
-template <class R>
+template <class R, bool FAST>
 __device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7]) {
     const R d = S - k.un;
-    const R chi = Ar<R>::div(d, S - Ss);
+    const R chi = Ar<R, FAST>::div(d, S - Ss);
     R us[5];
     us[0] = chi * k.U[0];
     us[1] = chi * k.U[1];
     us[2] = chi * (k.rho * Ss);
     us[3] = chi * (k.rho * k.ut);
-    us[4] = chi * (k.E + (Ss - k.un) * (k.rho * Ss + Ar<R>::div(k.p, d)));
+    us[4] = chi * (k.E + (Ss - k.un) * (k.rho * Ss + Ar<R, FAST>::div(k.p, d)));
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[c] = k.F[c] + S * (us[c] - k.U[c]);
     out[5] = k.un + S * (chi - R(1));
@@ -168,17 +182,17 @@ __device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7])
 // HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f).
 // The star state is evaluated once, for the side the contact moves away
 // from; only faces with S* == 0 exactly evaluate both sides and average.
-template <class R>
+template <class R, bool FAST>
 __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[6], R out[7]) {
     Side<R> L, Rs;
     R cL, cR;
-    side_eval<R>(m, wL, L, cL);
-    side_eval<R>(m, wR, Rs, cR);
+    side_eval<R, FAST>(m, wL, L, cL);
+    side_eval<R, FAST>(m, wR, Rs, cR);
     const R SL = fmin(L.un - cL, Rs.un - cR);
     const R SR = fmax(L.un + cL, Rs.un + cR);
     const R dL = SL - L.un;
     const R dR = SR - Rs.un;
-    const R Ss = Ar<R>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
+    const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
                             L.rho * dL - Rs.rho * dR);
     const bool useL = Ss > R(0);
     Side<R> K;
@@ -194,12 +208,12 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[
         K.F[c] = useL ? L.F[c] : Rs.F[c];
     }
     R st[7];
-    star_flux<R>(K, useL ? SL : SR, Ss, st);
+    star_flux<R, FAST>(K, useL ? SL : SR, Ss, st);
     if (!(Ss > R(0)) && !(Ss < R(0))) {
         // contact at rest relative to the face: average of both star branches
         R a[7], b[7];
-        star_flux<R>(L, SL, Ss, a);
-        star_flux<R>(Rs, SR, Ss, b);
+        star_flux<R, FAST>(L, SL, Ss, a);
+        star_flux<R, FAST>(Rs, SR, Ss, b);
 #pragma unroll
         for (int c = 0; c < 7; ++c) st[c] = R(0.5) * (a[c] + b[c]);
     }
@@ -226,12 +240,12 @@ __device__ __forceinline__ void update_cell(const S q[6], const R flo[7], const 
 // x sweep of one row of the strip.  All 256 threads call it (it holds
 // barriers); q: this thread's cell, qo: updated cell (valid for threads
 // 2..253; the halo threads return q unchanged).
-template <class S, class R, int LIM>
+template <class S, class R, bool FAST, int LIM>
 __device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
                                       const Mix<S> &ms, const Mix<R> &mr, R (*sWF)[kThreads],
                                       R (*sH)[kThreads]) {
     S w[6], r, rc2;
-    cons_to_prim<S>(ms, q, w, r, rc2);
+    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
     R wr[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -247,7 +261,7 @@ __device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
             wm[c] = sWF[c][t - 1];
             wp[c] = sWF[c][t + 1];
         }
-        face_states<R, LIM>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
+        face_states<R, FAST, LIM>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sH[c][t] = wh[c];
     }
@@ -257,7 +271,7 @@ __device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
         R whm[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) whm[c] = sH[c][t - 1];
-        hllc<R>(mr, whm, wl, f);
+        hllc<R, FAST>(mr, whm, wl, f);
 #pragma unroll
         for (int c = 0; c < 7; ++c) sWF[c][t] = f[c];
     }
@@ -277,7 +291,7 @@ __device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
 // y sweep as a rolling window down one column (registers only).  Rows are
 // pushed in order; after the 5th row the window yields the updated row two
 // behind the one pushed.  Values are in the y frame (normal momentum rho v).
-template <class S, class R, int LIM>
+template <class S, class R, bool FAST, int LIM>
 struct YPipe {
     S q1[6], q2[6];      // conserved rows k-1, k-2
     R w1[6], w2[6];      // primitives rows k-1, k-2
@@ -289,17 +303,17 @@ struct YPipe {
     __device__ __forceinline__ bool push(int cnt, const S qk[6], S qo[6], S lam, R hl,
                                          const Mix<S> &ms, const Mix<R> &mr) {
         S w[6], r, rc2;
-        cons_to_prim<S>(ms, qk, w, r, rc2);
+        cons_to_prim<S, FAST>(ms, qk, w, r, rc2);
         R wk[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) wk[c] = (R)w[c];
         bool out = false;
         if (cnt >= 2) {
             R wl[6], wh[6];
-            face_states<R, LIM>(w2, w1, wk, r1, c1, hl, wl, wh);
+            face_states<R, FAST, LIM>(w2, w1, wk, r1, c1, hl, wl, wh);
             if (cnt >= 3) {
                 R f[7];
-                hllc<R>(mr, wh2, wl, f);
+                hllc<R, FAST>(mr, wh2, wl, f);
                 if (cnt >= 4) {
                     update_cell<S, R>(q2, f2, f, lam, qo);
                     out = true;
@@ -326,15 +340,15 @@ template <class S> __device__ __forceinline__ void to_yframe(const S a[6], S b[6
 }
 
 // Pointwise stage and CFL contribution of one updated cell (U order).
-template <class S>
+template <class S, bool FAST>
 __device__ __forceinline__ void epilogue(S q[6], const Mix<S> &ms, S zlo, S zhi, S idx, S idy,
                                          S &smax, int &bad) {
     q[5] = fmin(fmax(q[5], zlo), zhi);
     S w[6], r, rc2;
-    cons_to_prim<S>(ms, q, w, r, rc2);
-    const S c = Ar<S>::sqrt_(rc2 * r);
+    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+    const S c = Ar<S, FAST>::sqrt_(rc2 * r);
     const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
-    if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S>::big())) bad = 1;
+    if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
     else smax = fmax(smax, s);
 }
 
@@ -368,14 +382,14 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 }
 
 // ------------------------------------------------------------------------
-// The state-update kernel.  MODE: kXY / kYX (fused step), kX / kY (one sweep).
-// FINAL: this pass produces the end-of-step state (pointwise stage + CFL).
-template <class S, class R, int LIM, int MODE, bool FINAL>
-__global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
-    __shared__ R sWF[7][kThreads];
-    __shared__ R sH[6][kThreads];
+// One tile of the state update: strip bx (252 written columns) and row
+// segment by of the solve described by d.  MODE: kXY / kYX (fused step), kX /
+// kY (one sweep).  FINAL: this pass produces the end-of-step state (pointwise
+// stage + CFL contribution).  All threads of the workgroup call it.
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+__device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
+                                         R (*sWF)[kThreads], R (*sH)[kThreads]) {
     Control *ctl = d.ctl;
-    if (ctl->skip) return;
     const S lamx = (S)ctl->lam_x, lamy = (S)ctl->lam_y;
     const R hlx = (R)ctl->hl_x, hly = (R)ctl->hl_y;
     const int slot = (int)((ctl->step_exec + 1) & 1);
@@ -386,11 +400,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
     S *dst = (S *)d.buf[src_idx ^ 1];
     const long long plane = d.plane;
     const int t = threadIdx.x;
-    const int x0 = blockIdx.x * kTileW;
+    const int x0 = bx * kTileW;
     const int col = x0 - kHalo + t;
     const int gcol = map_idx(col, d.nx, d.bc_xlo, d.bc_xhi);
     const bool out_col = (t >= kHalo) && (t < kThreads - kHalo) && (col < d.nx);
-    const int y0 = blockIdx.y * d.seg_h;
+    const int y0 = by * d.seg_h;
     const int y1 = min(y0 + d.seg_h, d.ny);
     const S zlo = (S)d.zlo, zhi = (S)d.zhi, idx = (S)d.idx, idy = (S)d.idy;
 
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
         for (int c = 0; c < 6; ++c) q[c] = src[c * plane + o];
     };
     auto store = [&](int k, S q[6]) {
-        if (FINAL) epilogue<S>(q, ms, zlo, zhi, idx, idy, smax, bad);
+        if (FINAL) epilogue<S, FAST>(q, ms, zlo, zhi, idx, idy, smax, bad);
         const long long o = (long long)k * d.pitch + col;
 #pragma unroll
         for (int c = 0; c < 6; ++c) dst[c * plane + o] = q[c];
@@ -418,11 +432,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) q[c] = qn[c];
             if (k + 1 < y1) load(k + 1, qn);
-            x_row<S, R, LIM>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            x_row<S, R, FAST, LIM>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
             if (out_col) store(k, qo);
         }
     } else {
-        YPipe<S, R, LIM> yp;
+        YPipe<S, R, FAST, LIM> yp;
         const int k0 = y0 - kHalo, k1 = y1 + kHalo;
         S qn[6];
         load(k0, qn);
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
             if (k + 1 < k1) load(k + 1, qn);
             if (MODE == kXY) {
                 S qs[6], qy[6], qo[6], qu[6];
-                x_row<S, R, LIM>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                x_row<S, R, FAST, LIM>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
                 to_yframe<S>(qs, qy);
                 if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
                     to_yframe<S>(qo, qu);
@@ -449,13 +463,38 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
                     if (got && out_col) store(k - kHalo, qu);
                 } else if (got) {  // kYX: x sweep of the row just finished in y
                     S qx[6];
-                    x_row<S, R, LIM>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    x_row<S, R, FAST, LIM>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
                     if (out_col) store(k - kHalo, qx);
                 }
             }
         }
     }
     if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
+}
+
+// State update of one solve: grid (strips, segments).
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+__global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
+    __shared__ R sWF[7][kThreads];
+    __shared__ R sH[6][kThreads];
+    if (d.ctl->skip) return;
+    run_tile<S, R, FAST, LIM, MODE, FINAL>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
+}
+
+// Fused state update of many solves in one launch: workgroup b takes tile
+// tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
+// (x-y order and source copy), read from its control block.
+template <class S, class R, bool FAST, int LIM>
+__global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
+                                                                const int4 *tiles) {
+    __shared__ R sWF[7][kThreads];
+    __shared__ R sH[6][kThreads];
+    const int4 tl = tiles[blockIdx.x];
+    const Desc d = descs[tl.x];
+    if (d.ctl->skip) return;
+    const int par = (int)(d.ctl->step_exec & 1);
+    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true>(d, tl.y, tl.z, 0, sWF, sH);
+    else run_tile<S, R, FAST, LIM, kYX, true>(d, tl.y, tl.z, 1, sWF, sH);
 }
 
 // ------------------------------------------------------------------------
@@ -502,6 +541,37 @@ __global__ void dt_kernel(Control *ctl, double cfl, double dx, double dy, double
     ctl->step_exec = n;
     ctl->step = n + 1;
     ctl->t = tn;
+    ctl->skip = 0;
+}
+
+// Time steps of many solves (one thread each, CFL steps, no end time).
+__global__ void batched_dt_kernel(const Desc *descs, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const Desc &d = descs[k];
+    Control *ctl = d.ctl;
+    const long long s = ctl->step;
+    if (ctl->err) {
+        ctl->skip = 1;
+        return;
+    }
+    const double smax = __longlong_as_double((long long)ctl->smax_bits[s & 1]);
+    if (!(smax > 0.0) || !(smax <= 1.0e300)) {
+        ctl->err |= 1;
+        ctl->skip = 1;
+        return;
+    }
+    const double dt = d.cfl / smax;
+    const double lx = dt / d.dx, ly = dt / d.dy;
+    ctl->dt = dt;
+    ctl->lam_x = lx;
+    ctl->lam_y = ly;
+    ctl->hl_x = 0.5 * lx;
+    ctl->hl_y = 0.5 * ly;
+    ctl->smax_bits[(s + 1) & 1] = 0ULL;
+    ctl->step_exec = s;
+    ctl->step = s + 1;
+    ctl->t = ctl->t + dt;
     ctl->skip = 0;
 }
 
@@ -557,7 +627,7 @@ __global__ void cons_from_f64_kernel(Desc d, int dst_idx, const double *cons) {
 }
 
 // CFL maximum of a state (no pointwise stage), into the slot of the current step.
-template <class S>
+template <class S, bool FAST>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, int slot) {
     const long long N = (long long)d.nx * d.ny;
     const S *src = (const S *)d.buf[src_idx];
@@ -573,10 +643,10 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, i
         S q[6], w[6], r, rc2;
 #pragma unroll
         for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
-        cons_to_prim<S>(ms, q, w, r, rc2);
-        const S c = Ar<S>::sqrt_(rc2 * r);
+        cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+        const S c = Ar<S, FAST>::sqrt_(rc2 * r);
         const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
-        if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S>::big())) bad = 1;
+        if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
         else smax = fmax(smax, s);
     }
     block_cfl_commit((double)smax, bad, d.ctl, slot);
@@ -600,14 +670,14 @@ __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
         S q[6], w[6], r, rc2;
 #pragma unroll
         for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
-        cons_to_prim<S>(ms, q, w, r, rc2);
+        cons_to_prim<S, false>(ms, q, w, r, rc2);
         double v;
         switch (field) {
             case 6: v = (double)(q[0] + q[1]); break;
             case 7: v = (double)w[2]; break;
             case 8: v = (double)w[3]; break;
             case 9: v = (double)w[4]; break;
-            default: v = (double)Ar<S>::sqrt_(rc2 * r); break;
+            default: v = (double)Ar<S, false>::sqrt_(rc2 * r); break;
         }
         out[k] = v;
     }
@@ -654,9 +724,11 @@ hipError_t launch_reduce(const Desc &d, int prec, int src, hipStream_t st) {
     // slot -1: the slot read by the next step, i.e. the parity of the
     // completed-step count held in the control block
     if (prec == kP32)
-        hipLaunchKernelGGL(reduce_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, src, -1);
+        hipLaunchKernelGGL((reduce_kernel<float, true>), dim3(g), dim3(kThreads), 0, st, d, src, -1);
+    else if (prec == kPMix)
+        hipLaunchKernelGGL((reduce_kernel<double, true>), dim3(g), dim3(kThreads), 0, st, d, src, -1);
     else
-        hipLaunchKernelGGL(reduce_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, src, -1);
+        hipLaunchKernelGGL((reduce_kernel<double, false>), dim3(g), dim3(kThreads), 0, st, d, src, -1);
     return hipGetLastError();
 }
 
@@ -666,19 +738,19 @@ hipError_t launch_dt(const Desc &d, double cfl, double dx, double dy, double dt_
     return hipGetLastError();
 }
 
-template <class S, class R, int LIM>
+template <class S, class R, bool FAST, int LIM>
 static void launch_step_t(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
     switch (mode) {
-        case kXY: hipLaunchKernelGGL((step_kernel<S, R, LIM, kXY, true>), grid, block, 0, st, d, src); break;
-        case kYX: hipLaunchKernelGGL((step_kernel<S, R, LIM, kYX, true>), grid, block, 0, st, d, src); break;
+        case kXY: hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kXY, true>), grid, block, 0, st, d, src); break;
+        case kYX: hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kYX, true>), grid, block, 0, st, d, src); break;
         case kX:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, LIM, kX, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, LIM, kX, false>), grid, block, 0, st, d, src);
+            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, true>), grid, block, 0, st, d, src);
+            else hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, false>), grid, block, 0, st, d, src);
             break;
         default:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, LIM, kY, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, LIM, kY, false>), grid, block, 0, st, d, src);
+            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, true>), grid, block, 0, st, d, src);
+            else hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, false>), grid, block, 0, st, d, src);
             break;
     }
 }
@@ -686,15 +758,41 @@ static void launch_step_t(const Desc &d, int mode, int final_pass, int src, hipS
 hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                        hipStream_t st) {
     if (prec == kP64) {
-        if (lim == 1) launch_step_t<double, double, 1>(d, mode, final_pass, src, st);
-        else launch_step_t<double, double, 0>(d, mode, final_pass, src, st);
+        if (lim == 1) launch_step_t<double, double, false, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<double, double, false, 0>(d, mode, final_pass, src, st);
     } else if (prec == kPMix) {
-        if (lim == 1) launch_step_t<double, float, 1>(d, mode, final_pass, src, st);
-        else launch_step_t<double, float, 0>(d, mode, final_pass, src, st);
+        if (lim == 1) launch_step_t<double, float, true, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<double, float, true, 0>(d, mode, final_pass, src, st);
     } else {
-        if (lim == 1) launch_step_t<float, float, 1>(d, mode, final_pass, src, st);
-        else launch_step_t<float, float, 0>(d, mode, final_pass, src, st);
+        if (lim == 1) launch_step_t<float, float, true, 1>(d, mode, final_pass, src, st);
+        else launch_step_t<float, float, true, 0>(d, mode, final_pass, src, st);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batched_dt_kernel, dim3((n + 63) / 64), dim3(64), 0, st, descs, n);
+    return hipGetLastError();
+}
+
+template <class S, class R, bool FAST>
+static void launch_batched_t(const Desc *descs, const int4 *tiles, int ntiles, int lim,
+                             hipStream_t st) {
+    if (lim == 1)
+        hipLaunchKernelGGL((batched_step_kernel<S, R, FAST, 1>), dim3(ntiles), dim3(kThreads), 0,
+                           st, descs, tiles);
+    else
+        hipLaunchKernelGGL((batched_step_kernel<S, R, FAST, 0>), dim3(ntiles), dim3(kThreads), 0,
+                           st, descs, tiles);
+}
+
+hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
+                               int lim, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    if (prec == kP64) launch_batched_t<double, double, false>(descs, tiles, ntiles, lim, st);
+    else if (prec == kPMix) launch_batched_t<double, float, true>(descs, tiles, ntiles, lim, st);
+    else launch_batched_t<float, float, true>(descs, tiles, ntiles, lim, st);
     return hipGetLastError();
 }
 

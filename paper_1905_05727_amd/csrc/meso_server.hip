@@ -1,0 +1,579 @@
+// meso_server.hip -- continuous-batching server of independent solves
+// (host side of the mf_server_* calls in include/meso.h).
+//
+// Device memory: one arena of hbm_budget bytes allocated at creation; every
+// admitted solve holds one block of it: control block, two state copies and a
+// dense FP64 read-back area (6 planes).  A first-fit free list with
+// coalescing manages the blocks, so admission can never exceed the budget.
+//
+// Per tick: finished read-backs are harvested (non-blocking event queries),
+// queued requests are admitted while a slot and a block are free (their
+// initial state is uploaded and converted on the compute stream, so they join
+// the very next batched launch), and one batched dt kernel plus one batched
+// state-update kernel advance every admitted solve by one step.  A solve whose
+// last step has been enqueued is converted to dense FP64 on the compute stream
+// and copied to pinned host memory on the read-back stream, overlapping the
+// following ticks.
+
+#include "meso.h"
+#include "meso_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+using meso::Control;
+using meso::Desc;
+
+namespace {
+
+constexpr int kServerSegH = 32;   // rows per workgroup segment for served solves
+
+struct Request {
+    uint64_t id;
+    mf_grid grid;
+    mf_material mat[2];
+    mf_options opt;
+    std::vector<double> prim;     // until admitted
+    int64_t nsteps;
+    int state;                    // MF_REQ_*
+    std::vector<double> result;   // 6 planes once done
+    double t_final;
+    int64_t steps_final;
+};
+
+struct Pinned {                   // reusable pinned host buffer
+    double *p;
+    size_t bytes;
+    hipEvent_t ev;                // last async copy that used it
+};
+
+struct Slot {
+    bool used;
+    uint64_t req;
+    size_t off, bytes;            // arena block
+    Desc d;
+    int64_t steps_enq;            // steps enqueued so far
+    int64_t nsteps;
+    bool draining;
+    int pin;                      // pinned buffer holding the read-back
+    hipEvent_t done;              // read-back copy finished
+};
+
+struct FreeList {                 // first-fit arena allocator with coalescing
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t in_use = 0, peak = 0;
+    void init(size_t n) {
+        free_.clear();
+        free_[0] = n;
+    }
+    bool alloc(size_t n, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n;
+                const size_t o2 = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o2] = rest;
+                in_use += n;
+                peak = std::max(peak, in_use);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        in_use -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+size_t readback_bytes(const mf_grid *g) {
+    return meso::round_up((size_t)6 * g->nx * (size_t)g->ny * sizeof(double), meso::kAlign);
+}
+
+}  // namespace
+
+struct mf_server {
+    mf_server_config cfg;
+    hipStream_t st;               // compute stream
+    hipStream_t rb;               // read-back stream
+    bool own_st;
+    char *arena;
+    FreeList fl;
+    std::vector<Slot> slots;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Request> reqs;
+    uint64_t next_id;
+    // batched launch tables
+    Desc *d_descs;
+    int4 *d_tiles;
+    size_t tiles_cap;
+    std::vector<Pinned> tab_pins;     // pinned staging of the tables, ring
+    size_t tab_next;
+    bool dirty;
+    int n_active;
+    int n_tiles;
+    int64_t active_cells;
+    // uploads of initial states
+    double *d_stage;
+    size_t stage_bytes;
+    std::vector<Pinned> up_pins;
+    size_t up_next;
+    // read-back pinned buffers
+    std::vector<Pinned> rb_pins;
+    std::vector<int> rb_free;
+    // in-flight tick events
+    std::deque<hipEvent_t> inflight;
+    std::vector<hipEvent_t> ev_pool;
+    // stats
+    int64_t ticks, cell_updates, completed;
+};
+
+namespace {
+
+int32_t dev_err(hipError_t e) { return e == hipSuccess ? MF_OK : MF_E_DEVICE; }
+
+hipEvent_t take_event(mf_server *s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// A pinned buffer of at least `bytes` from a ring: waits for its last copy.
+int32_t ring_pinned(std::vector<Pinned> &ring, size_t &next, size_t bytes, Pinned **out) {
+    Pinned &p = ring[next];
+    next = (next + 1) % ring.size();
+    if (hipEventSynchronize(p.ev) != hipSuccess) return MF_E_DEVICE;
+    if (p.bytes < bytes) {
+        if (p.p) (void)hipHostFree(p.p);
+        p.p = nullptr;
+        p.bytes = 0;
+        if (hipHostMalloc((void **)&p.p, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return MF_E_OUT_OF_MEMORY;
+        }
+        p.bytes = bytes;
+    }
+    *out = &p;
+    return MF_OK;
+}
+
+size_t request_bytes(const mf_grid *g, int prec) {
+    return meso::kAlign + 2 * meso::state_bytes(g, prec) + readback_bytes(g);
+}
+
+// Upload and convert a request's initial state into a free slot.
+int32_t admit_one(mf_server *s, Request &r, Slot &sl) {
+    const size_t n = (size_t)r.grid.nx * r.grid.ny * 6;
+    const size_t bytes = n * sizeof(double);
+    if (bytes > s->stage_bytes) {
+        if (s->d_stage) {
+            if (hipStreamSynchronize(s->st) != hipSuccess) return MF_E_DEVICE;
+            (void)hipFree(s->d_stage);
+        }
+        s->d_stage = nullptr;
+        s->stage_bytes = 0;
+        if (hipMalloc((void **)&s->d_stage, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return MF_E_OUT_OF_MEMORY;
+        }
+        s->stage_bytes = bytes;
+    }
+    Pinned *pp = nullptr;
+    int32_t rc = ring_pinned(s->up_pins, s->up_next, bytes, &pp);
+    if (rc != MF_OK) return rc;
+    memcpy(pp->p, r.prim.data(), bytes);
+    std::vector<double>().swap(r.prim);
+    hipError_t e = hipMemcpyAsync(s->d_stage, pp->p, bytes, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipEventRecord(pp->ev, s->st);
+    if (e == hipSuccess) e = meso::launch_init_control(sl.d, 0.0, 0, s->st);
+    if (e == hipSuccess) e = meso::launch_prim_to_cons(sl.d, s->cfg.precision, 0, s->d_stage, s->st);
+    if (e == hipSuccess) e = meso::launch_reduce(sl.d, s->cfg.precision, 0, s->st);
+    return dev_err(e);
+}
+
+int32_t admit(mf_server *s) {
+    while (!s->queue.empty()) {
+        int free_slot = -1;
+        for (size_t i = 0; i < s->slots.size(); ++i)
+            if (!s->slots[i].used) {
+                free_slot = (int)i;
+                break;
+            }
+        if (free_slot < 0) return MF_OK;
+        Request &r = s->reqs[s->queue.front()];
+        const size_t need = request_bytes(&r.grid, s->cfg.precision);
+        size_t off = 0;
+        if (!s->fl.alloc(need, &off)) return MF_OK;   // wait for memory
+        Slot &sl = s->slots[free_slot];
+        sl.used = true;
+        sl.req = r.id;
+        sl.off = off;
+        sl.bytes = need;
+        sl.steps_enq = 0;
+        sl.nsteps = r.nsteps;
+        sl.draining = false;
+        sl.pin = -1;
+        meso::fill_desc(sl.d, &r.grid, r.mat, &r.opt, s->arena + off, kServerSegH);
+        s->queue.pop_front();
+        r.state = MF_REQ_RUNNING;
+        const int32_t rc = admit_one(s, r, sl);
+        if (rc != MF_OK) return rc;
+        s->dirty = true;
+    }
+    return MF_OK;
+}
+
+// Rebuild the descriptor and tile tables of the advancing solves.
+int32_t rebuild_tables(mf_server *s) {
+    std::vector<Desc> descs;
+    std::vector<int4> tiles;
+    int64_t cells = 0;
+    for (auto &sl : s->slots) {
+        if (!sl.used || sl.draining) continue;
+        const int k = (int)descs.size();
+        descs.push_back(sl.d);
+        for (int by = 0; by < sl.d.nsegs; ++by)
+            for (int bx = 0; bx < sl.d.nstrips; ++bx) tiles.push_back(make_int4(k, bx, by, 0));
+        cells += (int64_t)sl.d.nx * sl.d.ny;
+    }
+    s->n_active = (int)descs.size();
+    s->n_tiles = (int)tiles.size();
+    s->active_cells = cells;
+    s->dirty = false;
+    if (descs.empty()) return MF_OK;
+    if (tiles.size() > s->tiles_cap) {
+        if (hipStreamSynchronize(s->st) != hipSuccess) return MF_E_DEVICE;
+        if (s->d_tiles) (void)hipFree(s->d_tiles);
+        s->d_tiles = nullptr;
+        size_t cap = std::max(tiles.size(), 2 * s->tiles_cap);
+        if (hipMalloc((void **)&s->d_tiles, cap * sizeof(int4)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->tiles_cap = 0;
+            return MF_E_OUT_OF_MEMORY;
+        }
+        s->tiles_cap = cap;
+    }
+    const size_t bd = descs.size() * sizeof(Desc), bt = tiles.size() * sizeof(int4);
+    Pinned *pp = nullptr;
+    int32_t rc = ring_pinned(s->tab_pins, s->tab_next, bd + bt, &pp);
+    if (rc != MF_OK) return rc;
+    memcpy(pp->p, descs.data(), bd);
+    memcpy((char *)pp->p + bd, tiles.data(), bt);
+    hipError_t e = hipMemcpyAsync(s->d_descs, pp->p, bd, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_tiles, (char *)pp->p + bd, bt, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipEventRecord(pp->ev, s->st);
+    return dev_err(e);
+}
+
+// The solve in `sl` has all its steps enqueued: convert and copy it back.
+int32_t start_drain(mf_server *s, Slot &sl) {
+    Request &r = s->reqs[sl.req];
+    const size_t n = (size_t)r.grid.nx * r.grid.ny;
+    const size_t bytes = 6 * n * sizeof(double) + sizeof(Control);
+    // a free pinned read-back buffer
+    int pin = -1;
+    for (size_t i = 0; i < s->rb_free.size(); ++i) {
+        if (s->rb_pins[s->rb_free[i]].bytes >= bytes) {
+            pin = s->rb_free[i];
+            s->rb_free.erase(s->rb_free.begin() + i);
+            break;
+        }
+    }
+    if (pin < 0) {
+        Pinned p{nullptr, 0, nullptr};
+        if (hipHostMalloc((void **)&p.p, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return MF_E_OUT_OF_MEMORY;
+        }
+        p.bytes = bytes;
+        s->rb_pins.push_back(p);
+        pin = (int)s->rb_pins.size() - 1;
+    }
+    sl.pin = pin;
+    sl.draining = true;
+    double *dense = (double *)(s->arena + sl.off + meso::kAlign + 2 * meso::state_bytes(&r.grid, s->cfg.precision));
+    const int src = (int)(sl.nsteps & 1);
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 6 && e == hipSuccess; ++f)
+        e = meso::launch_read_field(sl.d, s->cfg.precision, src, f, dense + f * n, s->st);
+    hipEvent_t conv = take_event(s);
+    if (!conv) return MF_E_DEVICE;
+    if (e == hipSuccess) e = hipEventRecord(conv, s->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->rb, conv, 0);
+    double *hp = s->rb_pins[pin].p;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp, dense, 6 * n * sizeof(double), hipMemcpyDeviceToHost, s->rb);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp + 6 * n, sl.d.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->rb);
+    sl.done = take_event(s);
+    if (!sl.done) return MF_E_DEVICE;
+    if (e == hipSuccess) e = hipEventRecord(sl.done, s->rb);
+    s->ev_pool.push_back(conv);   // reusable once recorded again later (stream order)
+    s->dirty = true;
+    return dev_err(e);
+}
+
+// Collect finished read-backs; wait = true blocks on each.
+int32_t harvest(mf_server *s, bool wait) {
+    for (auto &sl : s->slots) {
+        if (!sl.used || !sl.draining) continue;
+        hipError_t q = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return MF_E_DEVICE;
+        Request &r = s->reqs[sl.req];
+        const size_t n = (size_t)r.grid.nx * r.grid.ny;
+        const double *hp = s->rb_pins[sl.pin].p;
+        r.result.assign(hp, hp + 6 * n);
+        Control c;
+        memcpy(&c, hp + 6 * n, sizeof(Control));
+        r.t_final = c.t;
+        r.steps_final = c.step;
+        r.state = c.err ? MF_REQ_FAILED : MF_REQ_DONE;
+        s->rb_free.push_back(sl.pin);
+        s->ev_pool.push_back(sl.done);
+        s->fl.release(sl.off, sl.bytes);
+        sl.used = false;
+        sl.draining = false;
+        s->completed++;
+    }
+    return MF_OK;
+}
+
+void count(const mf_server *s, int32_t *active, int32_t *queued) {
+    int a = 0;
+    for (auto &sl : s->slots)
+        if (sl.used && !sl.draining) ++a;
+    if (active) *active = a;
+    if (queued) *queued = (int32_t)s->queue.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision) {
+    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
+    return request_bytes(grid, precision);
+}
+
+int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_server **out) {
+    if (!out) return MF_E_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg || cfg->hbm_budget < meso::kAlign || cfg->max_slots < 1 || cfg->max_slots > 65536 ||
+        cfg->precision < MF_FP64 || cfg->precision > MF_FP32 ||
+        (cfg->limiter != MF_LIM_VANLEER && cfg->limiter != MF_LIM_MINMOD) ||
+        cfg->max_inflight < 1 || cfg->max_inflight > 64)
+        return MF_E_INVALID_ARG;
+    mf_server *s = new (std::nothrow) mf_server();
+    if (!s) return MF_E_OUT_OF_MEMORY;
+    s->cfg = *cfg;
+    s->cfg.hbm_budget = cfg->hbm_budget / meso::kAlign * meso::kAlign;
+    s->next_id = 1;
+    s->own_st = hip_stream == nullptr;
+    hipError_t e = hipSuccess;
+    if (s->own_st) e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
+    else s->st = (hipStream_t)hip_stream;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->rb, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->arena, s->cfg.hbm_budget);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_descs, sizeof(Desc) * cfg->max_slots);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->arena) (void)hipFree(s->arena);
+        if (s->d_descs) (void)hipFree(s->d_descs);
+        if (s->rb) (void)hipStreamDestroy(s->rb);
+        if (s->own_st && s->st) (void)hipStreamDestroy(s->st);
+        delete s;
+        return e == hipErrorOutOfMemory ? MF_E_OUT_OF_MEMORY : MF_E_DEVICE;
+    }
+    s->fl.init(s->cfg.hbm_budget);
+    s->slots.assign(cfg->max_slots, Slot());
+    for (auto &sl : s->slots) sl.used = false;
+    const int ring = cfg->max_inflight + 2;
+    for (int i = 0; i < ring; ++i) {
+        Pinned a{nullptr, 0, nullptr}, b{nullptr, 0, nullptr};
+        (void)hipEventCreateWithFlags(&a.ev, hipEventDisableTiming);
+        (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+        s->tab_pins.push_back(a);
+        s->up_pins.push_back(b);
+    }
+    *out = s;
+    return MF_OK;
+}
+
+int32_t mf_server_submit(mf_server *s, const mf_grid *grid, const mf_material mat[2],
+                         const mf_options *opt, const double *prim, int64_t nsteps,
+                         uint64_t *ticket) {
+    if (!s || !prim || !ticket || nsteps < 1) return MF_E_INVALID_ARG;
+    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt))
+        return MF_E_INVALID_ARG;
+    if (opt->precision != s->cfg.precision || opt->limiter != s->cfg.limiter)
+        return MF_E_INVALID_ARG;
+    if (grid->nx > 1 << 15 || grid->ny > 1 << 15) return MF_E_INVALID_ARG;
+    if (request_bytes(grid, s->cfg.precision) > s->cfg.hbm_budget) return MF_E_OUT_OF_MEMORY;
+    Request r;
+    r.id = s->next_id++;
+    r.grid = *grid;
+    r.mat[0] = mat[0];
+    r.mat[1] = mat[1];
+    r.opt = *opt;
+    r.opt.fused = 1;
+    const size_t n = (size_t)grid->nx * grid->ny * 6;
+    r.prim.assign(prim, prim + n);
+    r.nsteps = nsteps;
+    r.state = MF_REQ_QUEUED;
+    r.t_final = 0.0;
+    r.steps_final = 0;
+    *ticket = r.id;
+    s->queue.push_back(r.id);
+    s->reqs.emplace(r.id, std::move(r));
+    return MF_OK;
+}
+
+int32_t mf_server_tick(mf_server *s, int32_t *active, int32_t *queued) {
+    if (!s) return MF_E_INVALID_ARG;
+    int32_t rc = harvest(s, false);
+    if (rc == MF_OK) rc = admit(s);
+    if (rc != MF_OK) return rc;
+    if (s->dirty) {
+        rc = rebuild_tables(s);
+        if (rc != MF_OK) return rc;
+    }
+    if (s->n_active > 0) {
+        if ((int)s->inflight.size() >= s->cfg.max_inflight) {
+            hipEvent_t old = s->inflight.front();
+            s->inflight.pop_front();
+            if (hipEventSynchronize(old) != hipSuccess) return MF_E_DEVICE;
+            s->ev_pool.push_back(old);
+        }
+        hipError_t e = meso::launch_batched_dt(s->d_descs, s->n_active, s->st);
+        if (e == hipSuccess)
+            e = meso::launch_batched_step(s->d_descs, s->d_tiles, s->n_tiles, s->cfg.precision,
+                                          s->cfg.limiter, s->st);
+        hipEvent_t ev = take_event(s);
+        if (!ev) return MF_E_DEVICE;
+        if (e == hipSuccess) e = hipEventRecord(ev, s->st);
+        if (e != hipSuccess) return MF_E_DEVICE;
+        s->inflight.push_back(ev);
+        s->ticks++;
+        s->cell_updates += s->active_cells;
+        for (auto &sl : s->slots) {
+            if (!sl.used || sl.draining) continue;
+            if (++sl.steps_enq == sl.nsteps) {
+                rc = start_drain(s, sl);
+                if (rc != MF_OK) return rc;
+            }
+        }
+    }
+    count(s, active, queued);
+    return MF_OK;
+}
+
+int32_t mf_server_poll(mf_server *s, uint64_t ticket, int32_t *state) {
+    if (!s || !state) return MF_E_INVALID_ARG;
+    int32_t rc = harvest(s, false);
+    if (rc != MF_OK) return rc;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return MF_E_INVALID_ARG;
+    *state = it->second.state;
+    return MF_OK;
+}
+
+int32_t mf_server_result(mf_server *s, uint64_t ticket, double *out_cons, size_t count_,
+                         double *t, int64_t *steps) {
+    if (!s) return MF_E_INVALID_ARG;
+    int32_t rc = harvest(s, false);
+    if (rc != MF_OK) return rc;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return MF_E_INVALID_ARG;
+    Request &r = it->second;
+    if (r.state == MF_REQ_QUEUED || r.state == MF_REQ_RUNNING) return MF_E_NOT_READY;
+    if (r.state == MF_REQ_FAILED) {
+        s->reqs.erase(it);
+        return MF_E_NONFINITE_STATE;
+    }
+    const size_t n = (size_t)r.grid.nx * r.grid.ny * 6;
+    if (!out_cons || count_ != n) return MF_E_INVALID_ARG;
+    memcpy(out_cons, r.result.data(), n * sizeof(double));
+    if (t) *t = r.t_final;
+    if (steps) *steps = r.steps_final;
+    s->reqs.erase(it);
+    return MF_OK;
+}
+
+int32_t mf_server_drain(mf_server *s) {
+    if (!s) return MF_E_INVALID_ARG;
+    for (;;) {
+        int32_t a = 0, q = 0;
+        int32_t rc = mf_server_tick(s, &a, &q);
+        if (rc != MF_OK) return rc;
+        if (a == 0 && q == 0) break;
+    }
+    return harvest(s, true);
+}
+
+int32_t mf_server_get_stats(mf_server *s, mf_server_stats *st) {
+    if (!s || !st) return MF_E_INVALID_ARG;
+    memset(st, 0, sizeof(*st));
+    st->ticks = s->ticks;
+    st->cell_updates = s->cell_updates;
+    st->completed = s->completed;
+    st->peak_bytes = (int64_t)s->fl.peak;
+    st->bytes_in_use = (int64_t)s->fl.in_use;
+    count(s, &st->active, &st->queued);
+    int dr = 0;
+    for (auto &sl : s->slots)
+        if (sl.used && sl.draining) ++dr;
+    st->draining = dr;
+    return MF_OK;
+}
+
+int32_t mf_server_destroy(mf_server *s) {
+    if (!s) return MF_E_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(s->st);
+    (void)hipStreamSynchronize(s->rb);
+    for (auto ev : s->inflight) (void)hipEventDestroy(ev);
+    for (auto ev : s->ev_pool) (void)hipEventDestroy(ev);
+    for (auto &sl : s->slots)
+        if (sl.used && sl.draining) (void)hipEventDestroy(sl.done);
+    for (auto *ring : {&s->tab_pins, &s->up_pins, &s->rb_pins})
+        for (auto &p : *ring) {
+            if (p.p) (void)hipHostFree(p.p);
+            if (p.ev) (void)hipEventDestroy(p.ev);
+        }
+    if (s->d_stage) (void)hipFree(s->d_stage);
+    if (s->d_tiles) (void)hipFree(s->d_tiles);
+    (void)hipFree(s->d_descs);
+    (void)hipFree(s->arena);
+    (void)hipStreamDestroy(s->rb);
+    if (s->own_st) (void)hipStreamDestroy(s->st);
+    delete s;
+    return dev_err(e);
+}
+
+}  // extern "C"

@@ -28,7 +28,10 @@ FIELDS = {"z1rho1": 0, "z2rho2": 1, "rhou": 2, "rhov": 3, "rhoE": 4, "z1": 5,
 EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conserved",
            "mf_set_time", "mf_step", "mf_run_steps", "mf_run_to_time", "mf_sync",
            "mf_read_field", "mf_read_conserved", "mf_get_time", "mf_enable_timing",
-           "mf_kernel_time", "mf_launch_info", "mf_destroy", "mf_status_str", "mf_version"]
+           "mf_kernel_time", "mf_launch_info", "mf_destroy", "mf_status_str", "mf_version",
+           "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
+           "mf_server_poll", "mf_server_result", "mf_server_drain", "mf_server_get_stats",
+           "mf_server_destroy"]
 
 
 class MesoError(RuntimeError):
@@ -45,6 +48,17 @@ class Grid(C.Structure):
 
 class Material(C.Structure):
     _fields_ = [("gamma", C.c_double), ("p_inf", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("precision", C.c_int32),
+                ("limiter", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("ticks", C.c_int64), ("cell_updates", C.c_int64), ("completed", C.c_int64),
+                ("peak_bytes", C.c_int64), ("bytes_in_use", C.c_int64), ("active", C.c_int32),
+                ("queued", C.c_int32), ("draining", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -86,6 +100,17 @@ def load_library():
         "mf_launch_info": (C.c_int32, [P, I64, I32, I32, I32]),
         "mf_destroy": (C.c_int32, [P]),
         "mf_status_str": (C.c_char_p, [C.c_int32]),
+        "mf_server_request_bytes": (C.c_size_t, [C.POINTER(Grid), C.c_int32]),
+        "mf_server_create": (C.c_int32, [C.POINTER(ServerConfig), P, C.POINTER(P)]),
+        "mf_server_submit": (C.c_int32, [P, C.POINTER(Grid), C.POINTER(Material),
+                                         C.POINTER(Options), D, C.c_int64,
+                                         C.POINTER(C.c_uint64)]),
+        "mf_server_tick": (C.c_int32, [P, I32, I32]),
+        "mf_server_poll": (C.c_int32, [P, C.c_uint64, I32]),
+        "mf_server_result": (C.c_int32, [P, C.c_uint64, D, C.c_size_t, D, I64]),
+        "mf_server_drain": (C.c_int32, [P]),
+        "mf_server_get_stats": (C.c_int32, [P, C.POINTER(ServerStats)]),
+        "mf_server_destroy": (C.c_int32, [P]),
         "mf_version": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

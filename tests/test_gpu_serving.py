@@ -1,0 +1,118 @@
+"""Continuous-batching server: every solve's result is identical alone and in
+the mix, admission stays inside the HBM budget, failures stay isolated."""
+import numpy as np
+import pytest
+
+from paper_1905_05727_amd import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1905_05727_amd import meso, serve  # noqa: E402
+
+import oracle  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def small_requests(n, seed=7, sizes=(48, 64, 100, 130, 260)):
+    rng = np.random.default_rng(seed)
+    return [S.serving_request(rng, sizes=sizes, steps=0) for _ in range(n)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_alone_equals_in_mix(prec):
+    reqs = small_requests(9)
+    nsteps = 37
+    say(f"case: 9 requests {[r.nx for r in reqs]}, {nsteps} steps, {prec}")
+    got = {}
+    with serve.Server(1 << 30, max_slots=5, precision=prec, max_inflight=3) as srv:
+        tickets = []
+        for k, sc in enumerate(reqs):
+            tickets.append(srv.submit(sc, nsteps))
+            for _ in range(k % 4):           # staggered arrivals: solves overlap at offsets
+                srv.tick()
+        srv.drain()
+        for k, tk in enumerate(tickets):
+            assert srv.poll(tk) == serve.REQ_DONE
+            got[k] = srv.result(tk)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["active"] == 0 and st["queued"] == 0
+    for k, sc in enumerate(reqs):
+        U, t, n = serve.solve_alone(sc, nsteps, precision=prec)
+        Ub, tb, nb = got[k]
+        assert n == nb == nsteps and t == tb
+        assert np.array_equal(U, Ub), f"request {k} ({sc.nx}^2) differs in the mix"
+    if prec == "fp64":
+        sc = reqs[0]
+        o = oracle.Oracle(oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl))
+        o.set_primitive(sc.prim)
+        o.run(nsteps)
+        assert np.array_equal(o.U, got[0][0])
+
+
+def test_admission_stays_within_budget():
+    reqs = small_requests(6, seed=11, sizes=(200,))
+    per = serve.Server.request_bytes(200, 200, "fp32_fp64acc")
+    budget = int(2.5 * per)
+    say(f"case: budget {budget} B = 2.5 requests")
+    with serve.Server(budget, max_slots=8, precision="fp32_fp64acc") as srv:
+        tks = [srv.submit(sc, 15) for sc in reqs]
+        peak_active = 0
+        while True:
+            a, q = srv.tick()
+            peak_active = max(peak_active, a)
+            if a == 0 and q == 0:
+                break
+        srv.drain()
+        st = srv.stats()
+        assert st["peak_bytes"] <= budget and peak_active == 2
+        for tk in tks:
+            assert srv.poll(tk) == serve.REQ_DONE
+            srv.result(tk)
+
+
+def test_failed_request_is_isolated():
+    reqs = small_requests(3, seed=3, sizes=(64,))
+    bad = reqs[1]
+    bad.prim = bad.prim.copy()
+    bad.prim[5, 5, 5] = np.nan
+    say("case: one NaN request among three")
+    with serve.Server(1 << 28, max_slots=4, precision="fp64") as srv:
+        tks = [srv.submit(sc, 12) for sc in reqs]
+        srv.drain()
+        assert srv.poll(tks[1]) == serve.REQ_FAILED
+        with pytest.raises(meso.MesoError) as ei:
+            srv.result(tks[1])
+        assert ei.value.status == -3
+        for k in (0, 2):
+            U, _, _ = srv.result(tks[k])
+            assert np.array_equal(U, serve.solve_alone(reqs[k], 12, "fp64")[0])
+
+
+def test_server_validation():
+    sc = small_requests(1)[0]
+    with serve.Server(1 << 20, max_slots=2, precision="fp32_fp64acc") as srv:
+        big = S.single_bubble(nx=1024, ny=512)
+        with pytest.raises(meso.MesoError) as ei:
+            srv.submit(big, 5)                     # can never fit in 1 MiB
+        assert ei.value.status == -2
+        srv.precision = "fp64"                     # options must match the server's
+        with pytest.raises(meso.MesoError) as ei:
+            srv.submit(sc, 5)
+        assert ei.value.status == -1
+
+
+def test_serve_poisson_replay():
+    reqs = small_requests(16, seed=5, sizes=(64, 128))
+    arr = S.poisson_arrivals(len(reqs), rate=400.0, seed=1)
+    say("case: 16 requests, Poisson 400/s, 60 steps")
+    with serve.Server(1 << 30, max_slots=8, precision="fp32_fp64acc") as srv:
+        res = serve.serve(srv, reqs, arr, 60)
+    assert np.all(res["latencies"] > 0) and res["p99_s"] >= res["p50_s"]
+    assert res["stats"]["completed"] == 16
