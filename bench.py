@@ -27,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# VALU issue peak for un-fused operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# (the published 78.6 TFLOP/s FP64 / 157.3 TFLOP/s FP32 count a fused
+# multiply-add, resp. a packed pair, as two or four flops)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# floating-point operations of one cell-step, counted from the arithmetic
+# contract (division and square root count as one): 2 sweeps x (closure 23 +
+# reconstruction/predictor 92 + HLLC 116 + update 22) + epilogue 35
+OPS_PER_CELL = 541
 BYTES_PER_CELL = {"fp64": 96, "fp32_fp64acc": 96, "fp32": 48}   # 1 read + 1 write of 6 planes
 DTYPE = {"fp64": "f64", "fp32_fp64acc": "f32/f64", "fp32": "f32"}
 METRIC = "cell-updates/s/GPU FP32 vs FP64 (+% HBM roofline); batched p50/p99 latency"
@@ -103,6 +111,52 @@ def copy_bandwidth(gib: float = 2.0, reps: int = 5):
     return {"bytes_per_launch": 2 * n * 8, "ms": ms, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}
 
 
+def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
+    """Serving workload: `nreq` independent shock-bubble solves of sizes
+    {128^2, 256^2, 512^2}, `nsteps` steps each.  Sequential capacity first
+    (solves back to back, one at a time, per-solve launches), then Poisson
+    arrivals at 0.8x and 2x that capacity through the batched server and
+    through the sequential baseline."""
+    from paper_1905_05727_amd import scenario, serve
+    t = time.perf_counter()
+    reqs = scenario.serving_workload(nreq, steps=nsteps)
+    log(f"serving: {nreq} requests generated ({time.perf_counter() - t:.1f} s)")
+    work = float(sum(r.nx * r.ny for r in reqs)) * nsteps
+    serve.solve_alone(reqs[0], 5, precision)          # warm up allocator and code objects
+    t = time.perf_counter()
+    for sc in reqs:
+        serve.solve_alone(sc, nsteps, precision)
+    t_seq = time.perf_counter() - t
+    cap = nreq / t_seq
+    log(f"serving: sequential back-to-back {t_seq:.2f} s -> capacity {cap:.1f} req/s, "
+        f"{work / t_seq / 1e9:.2f} G cell-updates/s")
+    out = {"requests": nreq, "steps": nsteps, "precision": precision,
+           "sizes": sorted({r.nx for r in reqs}), "cell_updates": work,
+           "sequential_capacity_req_per_s": cap,
+           "sequential_back_to_back_cell_updates_per_s": work / t_seq, "rates": {}}
+    budget = 16 << 30
+    for mult in (0.8, 2.0):
+        arr = scenario.poisson_arrivals(nreq, mult * cap)
+        with serve.Server(budget, max_slots=64, precision=precision, max_inflight=4) as srv:
+            b = serve.serve(srv, reqs, arr, nsteps)
+        sq = serve.serve_sequential(reqs, arr, nsteps, precision)
+        key = f"{mult}x"
+        out["rates"][key] = {
+            "arrival_rate_req_per_s": mult * cap,
+            "batched": {"p50_ms": 1e3 * b["p50_s"], "p99_ms": 1e3 * b["p99_s"],
+                        "cell_updates_per_s": b["cell_updates_per_s"],
+                        "makespan_s": b["makespan_s"],
+                        "peak_hbm_bytes": b["stats"]["peak_bytes"], "hbm_budget": budget,
+                        "ticks": b["stats"]["ticks"]},
+            "sequential": {"p50_ms": 1e3 * sq["p50_s"], "p99_ms": 1e3 * sq["p99_s"],
+                           "cell_updates_per_s": sq["cell_updates_per_s"],
+                           "makespan_s": sq["makespan_s"]}}
+        log(f"serving {key}: batched p50 {1e3 * b['p50_s']:.1f} ms p99 {1e3 * b['p99_s']:.1f} ms "
+            f"{b['cell_updates_per_s'] / 1e9:.2f} G/s | sequential p50 {1e3 * sq['p50_s']:.1f} ms "
+            f"p99 {1e3 * sq['p99_s']:.1f} ms {sq['cell_updates_per_s'] / 1e9:.2f} G/s")
+    return out
+
+
 def cpu_baseline(sc, nsteps):
     import oracle
     o = oracle.Oracle(oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl))
@@ -125,6 +179,9 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32_fp64acc,fp32")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-steps", type=int, default=500)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs one domain on one GPU; multi-GPU runs are not "
@@ -156,9 +213,11 @@ def main():
     for m, r in res.items():
         cups = N * args.steps / r["s"]
         ach = BYTES_PER_CELL[m] * N / (r["kernel_ms_avg"] * 1e-3) / 1e9
+        ops = OPS_PER_CELL * N / (r["kernel_ms_avg"] * 1e-3) / 1e12
         d = {"value": cups, "ms_per_step": 1e3 * r["s"] / args.steps,
              "kernel_ms": r["kernel_ms_avg"], "hbm_algorithmic_GBs": ach,
-             "roofline_frac": ach / HBM_PEAK_GBS, "dtype": DTYPE[m]}
+             "hbm_frac": ach / HBM_PEAK_GBS, "alu_TOPs": ops, "alu_frac": ops / ALU_PEAK_TOPS,
+             "dtype": DTYPE[m]}
         if ref is not None and m != "fp64":
             for k in ("rho", "p"):
                 d[f"rel_l1_{k}_vs_fp64"] = float(np.abs(r["fields"][k] - ref["fields"][k]).sum()
@@ -189,14 +248,18 @@ def main():
                                f"CFL 0.4, seed {sc.meta['seed']}",
                    "cells": N, "precision": head, "parallelism": "single GPU",
                    "launch": r["launch"]},
-        "roofline": {"bound": "hbm", "achieved": h["hbm_algorithmic_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": h["roofline_frac"],
+        "roofline": {"bound": "alu", "achieved": h["alu_TOPs"], "peak": ALU_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": h["alu_frac"],
                      "traffic": traffic_from_profiles(head),
                      "kernel": "step_kernel (fused x/y sweep)",
-                     "bytes_per_cell": BYTES_PER_CELL[head],
-                     "copy_kernel_GBs": cp["GBs"]},
+                     "ops_per_cell": OPS_PER_CELL,
+                     "hbm": {"achieved_GBs": h["hbm_algorithmic_GBs"], "peak_GBs": HBM_PEAK_GBS,
+                             "frac": h["hbm_frac"], "bytes_per_cell": BYTES_PER_CELL[head],
+                             "copy_kernel_GBs": cp["GBs"]}},
         "modes": mode_out,
     }
+    if not args.no_serving:
+        line["serving"] = serving_bench(args.serving_requests, args.serving_steps)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)

@@ -1,37 +1,53 @@
 """Build step of the HIP library (hipcc, gfx950).
 
-The shared library libmeso.so is built in-tree next to this file.  FP64 parity
-with the arithmetic contract needs IEEE division/square root and no
-contraction, hence -ffp-contract=off and no fast-math.  Packed FP32
-instructions are disabled (-packed-fp32-ops).
+The shared library libmeso.so is built in-tree next to this file from four
+translation units.  The FP64 kernels and the host code are compiled with
+-ffp-contract=off (every operation rounds separately, so the FP64 mode
+follows the arithmetic contract bit for bit); the FP32-bulk / FP32 kernels
+with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
+packed FP32 instructions are disabled (-packed-fp32-ops).
 """
 from __future__ import annotations
 
 import os
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmeso.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("meso_kernels.hip", "meso_api.hip", "meso_server.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-         "-ffp-contract=off", "-fno-fast-math",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument",
-         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+# (source, floating-point contraction)
+UNITS = [("meso_kernels.hip", "off"), ("meso_kernels_fast.hip", "fast"),
+         ("meso_api.hip", "off"), ("meso_server.hip", "off")]
+
+COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fno-fast-math",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-command-line-argument",
+          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libmeso.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    """Compile every HIP source and link libmeso.so (always recompiles)."""
+    with tempfile.TemporaryDirectory(prefix="meso_build_") as tmp:
+        objs = []
+        for src, contract in UNITS:
+            obj = os.path.join(tmp, src.replace(".hip", ".o"))
+            cmd = [HIPCC, *COMMON, f"-ffp-contract={contract}", "-c", "-o", obj,
+                   os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            objs.append(obj)
+        out = LIB + ".tmp"
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out, LIB)
     return LIB
 
 

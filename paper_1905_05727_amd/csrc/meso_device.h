@@ -1,0 +1,523 @@
+// meso_device.h -- device code of the two-fluid finite-volume update,
+// included by the two kernel translation units (meso_kernels.hip, built
+// without floating-point contraction for the FP64 mode; meso_kernels_fast.hip,
+// built with contraction for the FP32-bulk and FP32 modes).
+//
+// Equations: inert part of Eq. (1) (Sec. 2.1) -- partial densities, momentum,
+// total energy, non-conservative advection of the air volume fraction z1 --
+// with the pressure-equilibrium closure of Sec. 2.1 and stiffened-gas phases
+// (Eq. (2) with constant reference terms, Sec. 2.2).  Scheme of Sec. 3:
+// MUSCL-Hancock in primitive variables, van Leer or minmod slopes, HLLC flux
+// with the HLLC-consistent interface velocity for the z1 term, dimensionally
+// split sweeps (x then y on even steps, y then x on odd ones), CFL time step
+// and the pointwise stage of the Strang split (z1 clamp when inert).
+//
+// Data layout in HBM: structure of arrays, 6 planes (z1 rho1, z2 rho2, rho u,
+// rho v, rho E, z1), rows padded to a multiple of 64 elements; two state copies
+// used as ping-pong buffers.
+//
+// Step kernel: a workgroup of 256 threads (4 wave64) owns a strip of 256
+// columns (252 written + 2 halo columns per side) and marches down a segment
+// of rows.  The x sweep of a row exchanges primitives, face states and fluxes
+// between neighbouring threads through LDS; the y sweep is a per-thread
+// rolling window held in registers (no exchange at all).  A fused step runs
+// both sweeps in one pass over the segment, so the state is read and written
+// once per step; the pointwise stage and the next step's CFL maximum are
+// computed in the epilogue from the values about to be stored.
+//
+// Precision is a template parameter of the same code: S is the storage /
+// accumulation type, R the type of reconstruction, predictor and Riemann
+// solver.  FP64 (S = R = double) follows the arithmetic contract operation
+// by operation (no contraction, IEEE division and square root).  The FP32
+// flux path uses the hardware reciprocal and square root.
+
+#pragma once
+
+#include "meso_internal.h"
+
+#include <float.h>
+
+namespace meso {
+
+// ------------------------------------------------------------------------
+// Arithmetic policies.  Ar<double, false>: IEEE division and square root (the
+// FP64 mode, bit-compatible with the arithmetic contract).  Ar<double, true>:
+// hardware reciprocal refined by one Newton step and the hardware square
+// root (the FP64 closure of the FP32-bulk mode).  Ar<float, *>: hardware
+// reciprocal and square root.
+template <class T, bool FAST> struct Ar;
+template <> struct Ar<double, false> {
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
+    static __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
+    static __device__ __forceinline__ double big() { return 1.0e300; }
+};
+template <> struct Ar<double, true> {
+    static __device__ __forceinline__ double rcp(double a) {
+        const double r = __builtin_amdgcn_rcp(a);
+        const double e = __builtin_fma(-a, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
+    static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
+    static __device__ __forceinline__ double sqrt_(double a) { return __builtin_amdgcn_sqrt(a); }
+    static __device__ __forceinline__ double rsq(double a) { return __builtin_amdgcn_rsq(a); }
+    static __device__ __forceinline__ double big() { return 1.0e300; }
+};
+template <bool FAST> struct Ar<float, FAST> {
+    static __device__ __forceinline__ float div(float a, float b) {
+        return a * __builtin_amdgcn_rcpf(b);
+    }
+    static __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+    static __device__ __forceinline__ float sqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
+    static __device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
+    static __device__ __forceinline__ float big() { return FLT_MAX; }
+};
+
+template <class T> struct Mix {
+    T g1, g2, h1, h2;
+};
+
+template <class T> __device__ __forceinline__ Mix<T> mix_of(const Desc &d) {
+    Mix<T> m;
+    m.g1 = (T)d.g1; m.g2 = (T)d.g2; m.h1 = (T)d.h1; m.h2 = (T)d.h2;
+    return m;
+}
+
+// Ghost-cell index map: transmissive copies the edge cell, periodic wraps.
+__device__ __forceinline__ int map_idx(int i, int n, int bc_lo, int bc_hi) {
+    if (i < 0) return bc_lo ? ((i % n) + n) % n : 0;
+    if (i >= n) return bc_hi ? i % n : n - 1;
+    return i;
+}
+
+// ------------------------------------------------------------------------
+// Closure (Sec. 2.1): sweep-frame conserved q = (a1, a2, mn, mt, E, z) to
+// primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2.
+template <class S, bool FAST>
+__device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[6], S &r,
+                                             S &rc2) {
+    const S rho = q[0] + q[1];
+    const S z = q[5];
+    const S z2 = S(1) - z;
+    const S xi = z * m.g1 + z2 * m.g2;
+    const S eta = z * m.h1 + z2 * m.h2;
+    S ixi;
+    if constexpr (FAST) {   // one reciprocal for both 1/rho and 1/xi
+        const S inv = Ar<S, FAST>::rcp(rho * xi);
+        r = xi * inv;
+        ixi = rho * inv;
+    } else {
+        r = Ar<S, FAST>::rcp(rho);
+        ixi = Ar<S, FAST>::rcp(xi);
+    }
+    const S un = q[2] * r;
+    const S ut = q[3] * r;
+    const S ke = S(0.5) * (q[2] * un + q[3] * ut);
+    const S rhoe = q[4] - ke;
+    const S p = (rhoe - eta) * ixi;
+    rc2 = (p * (S(1) + xi) + eta) * ixi;
+    w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
+}
+
+// Slope limiter (Sec. 3): a backward, b forward difference.
+template <class R, bool FAST, int LIM>
+__device__ __forceinline__ R limit(R a, R b) {
+    const R ab = a * b;
+    R s;
+    if (LIM == 1) {
+        s = (a > R(0)) ? fmin(a, b) : fmax(a, b);
+    } else {
+        s = Ar<R, FAST>::div(ab + ab, a + b);
+    }
+    return (ab > R(0)) ? s : R(0);
+}
+
+// MUSCL reconstruction and Hancock half step in primitive variables.
+template <class R, bool FAST, int LIM>
+__device__ __forceinline__ void face_states(const R wm[6], const R w0[6], const R wp[6], R r,
+                                            R rc2, R hl, R wl[6], R wh[6]) {
+    R d[6], s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d[c] = limit<R, FAST, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
+    const R un = w0[2];
+    s[0] = hl * (un * d[0] + w0[0] * d[2]);
+    s[1] = hl * (un * d[1] + w0[1] * d[2]);
+    s[2] = hl * (un * d[2] + r * d[4]);
+    s[3] = hl * (un * d[3]);
+    s[4] = hl * (un * d[4] + rc2 * d[2]);
+    s[5] = hl * (un * d[5]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        wl[c] = (w0[c] - R(0.5) * d[c]) - s[c];
+        wh[c] = (w0[c] + R(0.5) * d[c]) - s[c];
+    }
+}
+
+template <class R> struct Side {
+    R rho, un, ut, p, z, E;
+    R U[5], F[5];
+};
+
+template <class R, bool FAST>
+__device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R> &s, R &c) {
+    const R rho = w[0] + w[1];
+    const R un = w[2], ut = w[3], p = w[4], z = w[5];
+    const R z2 = R(1) - z;
+    const R xi = z * m.g1 + z2 * m.g2;
+    const R eta = z * m.h1 + z2 * m.h2;
+    const R num = p * (R(1) + xi) + eta;
+    if constexpr (FAST) c = num * Ar<R, FAST>::rsq(num * (xi * rho));   // sqrt(num / (xi rho))
+    else c = Ar<R, FAST>::sqrt_(Ar<R, FAST>::div(num, xi * rho));
+    const R E = (p * xi + eta) + R(0.5) * (rho * (un * un + ut * ut));
+    const R mn = rho * un;
+    s.rho = rho; s.un = un; s.ut = ut; s.p = p; s.z = z; s.E = E;
+    s.U[0] = w[0]; s.U[1] = w[1]; s.U[2] = mn; s.U[3] = rho * ut; s.U[4] = E;
+    s.F[0] = w[0] * un;
+    s.F[1] = w[1] * un;
+    s.F[2] = mn * un + p;
+    s.F[3] = mn * ut;
+    s.F[4] = (E + p) * un;
+}
+
+template <class R, bool FAST>
+__device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7]) {
+    const R d = S - k.un;
+    R chi;
+    R us[5];
+    if constexpr (FAST) {   // chi/d = 1/(S - S*): one reciprocal for the whole star state
+        const R inv = Ar<R, FAST>::rcp(S - Ss);
+        chi = d * inv;
+        us[4] = chi * k.E + (Ss - k.un) * (chi * (k.rho * Ss) + k.p * inv);
+    } else {
+        chi = Ar<R, FAST>::div(d, S - Ss);
+        us[4] = chi * (k.E + (Ss - k.un) * (k.rho * Ss + Ar<R, FAST>::div(k.p, d)));
+    }
+    us[0] = chi * k.U[0];
+    us[1] = chi * k.U[1];
+    us[2] = chi * (k.rho * Ss);
+    us[3] = chi * (k.rho * k.ut);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = k.F[c] + S * (us[c] - k.U[c]);
+    out[5] = k.un + S * (chi - R(1));
+    out[6] = k.z;
+}
+
+// HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f).
+// The star state is evaluated once, for the side the contact moves away
+// from; only faces with S* == 0 exactly evaluate both sides and average.
+template <class R, bool FAST>
+__device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[6], R out[7]) {
+    Side<R> L, Rs;
+    R cL, cR;
+    side_eval<R, FAST>(m, wL, L, cL);
+    side_eval<R, FAST>(m, wR, Rs, cR);
+    const R SL = fmin(L.un - cL, Rs.un - cR);
+    const R SR = fmax(L.un + cL, Rs.un + cR);
+    const R dL = SL - L.un;
+    const R dR = SR - Rs.un;
+    const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
+                            L.rho * dL - Rs.rho * dR);
+    const bool useL = Ss > R(0);
+    Side<R> K;
+    K.rho = useL ? L.rho : Rs.rho;
+    K.un = useL ? L.un : Rs.un;
+    K.ut = useL ? L.ut : Rs.ut;
+    K.p = useL ? L.p : Rs.p;
+    K.z = useL ? L.z : Rs.z;
+    K.E = useL ? L.E : Rs.E;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        K.U[c] = useL ? L.U[c] : Rs.U[c];
+        K.F[c] = useL ? L.F[c] : Rs.F[c];
+    }
+    R st[7];
+    star_flux<R, FAST>(K, useL ? SL : SR, Ss, st);
+    if (!(Ss > R(0)) && !(Ss < R(0))) {
+        // contact at rest relative to the face: average of both star branches
+        R a[7], b[7];
+        star_flux<R, FAST>(L, SL, Ss, a);
+        star_flux<R, FAST>(Rs, SR, Ss, b);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) st[c] = R(0.5) * (a[c] + b[c]);
+    }
+    const bool supL = SL >= R(0);
+    const bool supR = !supL && (SR <= R(0));
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = supL ? L.F[c] : (supR ? Rs.F[c] : st[c]);
+    out[5] = supL ? L.un : (supR ? Rs.un : st[5]);
+    out[6] = supL ? L.z : (supR ? Rs.z : st[6]);
+}
+
+// Update of one cell from its low- and high-face fluxes; fluxes are widened to
+// the storage type before they are differenced.
+template <class S, class R>
+__device__ __forceinline__ void update_cell(const S q[6], const R flo[7], const R fhi[7], S lam,
+                                            S qo[6]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qo[c] = q[c] - lam * ((S)fhi[c] - (S)flo[c]);
+    const S z = q[5];
+    qo[5] = z - lam * (((S)fhi[6] - z) * (S)fhi[5] - ((S)flo[6] - z) * (S)flo[5]);
+}
+
+// ------------------------------------------------------------------------
+// x sweep of one row of the strip.  All 256 threads call it (it holds
+// barriers); q: this thread's cell, qo: updated cell (valid for threads
+// 2..253; the halo threads return q unchanged).
+template <class S, class R, bool FAST, int LIM>
+__device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
+                                      const Mix<S> &ms, const Mix<R> &mr, R (*sWF)[kThreads],
+                                      R (*sH)[kThreads]) {
+    S w[6], r, rc2;
+    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+    R wr[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        wr[c] = (R)w[c];
+        sWF[c][t] = wr[c];
+    }
+    __syncthreads();
+    R wl[6], wh[6];
+    if (t >= 1 && t <= kThreads - 2) {
+        R wm[6], wp[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            wm[c] = sWF[c][t - 1];
+            wp[c] = sWF[c][t + 1];
+        }
+        face_states<R, FAST, LIM>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sH[c][t] = wh[c];
+    }
+    __syncthreads();
+    R f[7];
+    if (t >= 2 && t <= kThreads - 2) {
+        R whm[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) whm[c] = sH[c][t - 1];
+        hllc<R, FAST>(mr, whm, wl, f);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sWF[c][t] = f[c];
+    }
+    __syncthreads();
+    if (t >= 2 && t <= kThreads - 3) {
+        R fh[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) fh[c] = sWF[c][t + 1];
+        update_cell<S, R>(q, f, fh, lam, qo);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) qo[c] = q[c];
+    }
+    __syncthreads();
+}
+
+// y sweep as a rolling window down one column (registers only).  Rows are
+// pushed in order; after the 5th row the window yields the updated row two
+// behind the one pushed.  Values are in the y frame (normal momentum rho v).
+template <class S, class R, bool FAST, int LIM>
+struct YPipe {
+    S q1[6], q2[6];      // conserved rows k-1, k-2
+    R w1[6], w2[6];      // primitives rows k-1, k-2
+    R r1, c1;            // 1/rho and rho c^2 of row k-1
+    R wh2[6];            // high-face state of row k-2
+    R f2[7];             // flux through the low face of row k-2
+
+    // cnt = number of rows pushed before this one (uniform across the block)
+    __device__ __forceinline__ bool push(int cnt, const S qk[6], S qo[6], S lam, R hl,
+                                         const Mix<S> &ms, const Mix<R> &mr) {
+        S w[6], r, rc2;
+        cons_to_prim<S, FAST>(ms, qk, w, r, rc2);
+        R wk[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) wk[c] = (R)w[c];
+        bool out = false;
+        if (cnt >= 2) {
+            R wl[6], wh[6];
+            face_states<R, FAST, LIM>(w2, w1, wk, r1, c1, hl, wl, wh);
+            if (cnt >= 3) {
+                R f[7];
+                hllc<R, FAST>(mr, wh2, wl, f);
+                if (cnt >= 4) {
+                    update_cell<S, R>(q2, f2, f, lam, qo);
+                    out = true;
+                }
+#pragma unroll
+                for (int c = 0; c < 7; ++c) f2[c] = f[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) wh2[c] = wh[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            q2[c] = q1[c]; q1[c] = qk[c];
+            w2[c] = w1[c]; w1[c] = wk[c];
+        }
+        r1 = (R)r;
+        c1 = (R)rc2;
+        return out;
+    }
+};
+
+template <class S> __device__ __forceinline__ void to_yframe(const S a[6], S b[6]) {
+    b[0] = a[0]; b[1] = a[1]; b[2] = a[3]; b[3] = a[2]; b[4] = a[4]; b[5] = a[5];
+}
+
+// Pointwise stage and CFL contribution of one updated cell (U order).
+template <class S, bool FAST>
+__device__ __forceinline__ void epilogue(S q[6], const Mix<S> &ms, S zlo, S zhi, S idx, S idy,
+                                         S &smax, int &bad) {
+    q[5] = fmin(fmax(q[5], zlo), zhi);
+    S w[6], r, rc2;
+    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+    const S c = Ar<S, FAST>::sqrt_(rc2 * r);
+    const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
+    if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
+    else smax = fmax(smax, s);
+}
+
+// Workgroup max of the CFL bound folded into the control block.
+__device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *ctl, int slot) {
+    __shared__ double red_s[kThreads / 64];
+    __shared__ int red_b[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        smax = fmax(smax, __shfl_xor(smax, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red_s[wv] = smax;
+        red_b[wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red_s[0];
+        int b = red_b[0];
+        for (int i = 1; i < kThreads / 64; ++i) {
+            m = fmax(m, red_s[i]);
+            b |= red_b[i];
+        }
+        unsigned long long bits = b ? 0x7FF8000000000000ULL
+                                    : (unsigned long long)__double_as_longlong(m);
+        atomicMax(&ctl->smax_bits[slot], bits);
+        if (b) atomicOr(&ctl->err, 1);
+    }
+}
+
+// ------------------------------------------------------------------------
+// One tile of the state update: strip bx (252 written columns) and row
+// segment by of the solve described by d.  MODE: kXY / kYX (fused step), kX /
+// kY (one sweep).  FINAL: this pass produces the end-of-step state (pointwise
+// stage + CFL contribution).  All threads of the workgroup call it.
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+__device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
+                                         R (*sWF)[kThreads], R (*sH)[kThreads]) {
+    Control *ctl = d.ctl;
+    const S lamx = (S)ctl->lam_x, lamy = (S)ctl->lam_y;
+    const R hlx = (R)ctl->hl_x, hly = (R)ctl->hl_y;
+    const int slot = (int)((ctl->step_exec + 1) & 1);
+
+    const Mix<S> ms = mix_of<S>(d);
+    const Mix<R> mr = mix_of<R>(d);
+    const S *src = (const S *)d.buf[src_idx];
+    S *dst = (S *)d.buf[src_idx ^ 1];
+    const long long plane = d.plane;
+    const int t = threadIdx.x;
+    const int x0 = bx * kTileW;
+    const int col = x0 - kHalo + t;
+    const int gcol = map_idx(col, d.nx, d.bc_xlo, d.bc_xhi);
+    const bool out_col = (t >= kHalo) && (t < kThreads - kHalo) && (col < d.nx);
+    const int y0 = by * d.seg_h;
+    const int y1 = min(y0 + d.seg_h, d.ny);
+    const S zlo = (S)d.zlo, zhi = (S)d.zhi, idx = (S)d.idx, idy = (S)d.idy;
+
+    S smax = S(0);
+    int bad = 0;
+
+    auto load = [&](int k, S q[6]) {
+        const int gk = map_idx(k, d.ny, d.bc_ylo, d.bc_yhi);
+        const long long o = (long long)gk * d.pitch + gcol;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = src[c * plane + o];
+    };
+    auto store = [&](int k, S q[6]) {
+        if (FINAL) epilogue<S, FAST>(q, ms, zlo, zhi, idx, idy, smax, bad);
+        const long long o = (long long)k * d.pitch + col;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) dst[c * plane + o] = q[c];
+    };
+
+    if (MODE == kX) {
+        S qn[6];
+        load(y0, qn);
+        for (int k = y0; k < y1; ++k) {
+            S q[6], qo[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            if (k + 1 < y1) load(k + 1, qn);
+            x_row<S, R, FAST, LIM>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            if (out_col) store(k, qo);
+        }
+    } else {
+        YPipe<S, R, FAST, LIM> yp;
+        const int k0 = y0 - kHalo, k1 = y1 + kHalo;
+        S qn[6];
+        load(k0, qn);
+        for (int k = k0; k < k1; ++k) {
+            const int cnt = k - k0;
+            S q[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            if (k + 1 < k1) load(k + 1, qn);
+            if (MODE == kXY) {
+                S qs[6], qy[6], qo[6], qu[6];
+                x_row<S, R, FAST, LIM>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                to_yframe<S>(qs, qy);
+                if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
+                    to_yframe<S>(qo, qu);
+                    if (out_col) store(k - kHalo, qu);
+                }
+            } else {
+                S qy[6], qo[6], qu[6];
+                to_yframe<S>(q, qy);
+                const bool got = yp.push(cnt, qy, qo, lamy, hly, ms, mr);
+                to_yframe<S>(qo, qu);
+                if (MODE == kY) {
+                    if (got && out_col) store(k - kHalo, qu);
+                } else if (got) {  // kYX: x sweep of the row just finished in y
+                    S qx[6];
+                    x_row<S, R, FAST, LIM>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    if (out_col) store(k - kHalo, qx);
+                }
+            }
+        }
+    }
+    if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
+}
+
+// State update of one solve: grid (strips, segments).
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+__global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
+    __shared__ R sWF[7][kThreads];
+    __shared__ R sH[6][kThreads];
+    if (d.ctl->skip) return;
+    run_tile<S, R, FAST, LIM, MODE, FINAL>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
+}
+
+// Fused state update of many solves in one launch: workgroup b takes tile
+// tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
+// (x-y order and source copy), read from its control block.
+template <class S, class R, bool FAST, int LIM>
+__global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
+                                                                const int4 *tiles) {
+    __shared__ R sWF[7][kThreads];
+    __shared__ R sH[6][kThreads];
+    const int4 tl = tiles[blockIdx.x];
+    const Desc d = descs[tl.x];
+    if (d.ctl->skip) return;
+    const int par = (int)(d.ctl->step_exec & 1);
+    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true>(d, tl.y, tl.z, 0, sWF, sH);
+    else run_tile<S, R, FAST, LIM, kYX, true>(d, tl.y, tl.z, 1, sWF, sH);
+}
+
+}  // namespace meso

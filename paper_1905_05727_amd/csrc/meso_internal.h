@@ -87,5 +87,10 @@ hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double
 hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
                                int lim, hipStream_t st);
+// The FP32-bulk and FP32 instantiations (meso_kernels_fast.hip).
+hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+                            hipStream_t st);
+hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
+                                    int lim, hipStream_t st);
 
 }  // namespace meso
