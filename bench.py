@@ -46,7 +46,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("meso_kernels.hip", "meso_internal.h"):
+    for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -289,6 +289,88 @@ def poisson_arrivals(n: int, rate: float, seed: int = SEEDS["serving"]) -> np.nd
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
+# --------------------------------------------------------------------------
+# Paper-shaped cavity fields (Sec. 2.4, Sec. 3, App. A), water/air instead of
+# nitromethane/air.  Lengths in cells: the paper resolves a cavity diameter by
+# 100 cells (dx = 1 um for d_c = 100 um).
+def _paint_bubble_periodic_y(w: np.ndarray, xc: float, yc: float, R: float) -> None:
+    ny = w.shape[0]
+    for shift in (-ny, 0, ny):
+        if yc + shift + R + 16.0 >= 0.0 and yc + shift - R - 16.0 <= ny:
+            _paint_bubble(w, xc, yc + shift, R)
+
+
+def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip: int = 500,
+                  p_shock: float = 1.0e9, dx: float = 1.0e-6, eps: float = Z_EPS,
+                  steps: int = 0) -> Scenario:
+    """Square array of equal cavities (Sec. 2.4, Fig. 1(b)): spacing from
+    Eq. (6_1), domain width = one spacing with periodic top/bottom walls, a
+    shocked strip of `strip` cells at the transmissive left wall."""
+    delta = regular_spacing(float(d_c), phi)
+    ny = int(round(delta))
+    nx = int(length)
+    prim = _blank(nx, ny)
+    rho1, u1, S = stiffened_gas_shock(p_shock)
+    prim[2, :, :strip] = rho1
+    prim[3, :, :strip] = u1
+    prim[5, :, :strip] = p_shock
+    R = 0.5 * d_c
+    x = strip + 0.5 * delta
+    centres = []
+    while x + R + 2.0 <= nx:
+        _paint_bubble_periodic_y(prim[0], x, 0.5 * ny, R)
+        centres.append((x, 0.5 * ny, R))
+        x += delta
+    return Scenario("regular_array", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                    bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
+                    meta=dict(spacing=delta, ncavities=len(centres), p_shock=p_shock,
+                              shock_speed=S, bubbles=np.array(centres)))
+
+
+def random_cavities(d_c: int = 100, phi: float = 0.08, length: int = 24000, width: int = 2000,
+                    strip: int = 500, min_spacing: float = 2.5, p_shock: float = 1.0e9,
+                    dx: float = 1.0e-6, seed: int = 1905, eps: float = Z_EPS,
+                    steps: int = 0, max_draws: int = 2_000_000) -> Scenario:
+    """Random field of equal cavities (Sec. 2.4, Fig. 1(c)): the count from
+    Eq. (7) over the region ahead of the shocked strip, centres uniform with a
+    minimum centre-to-centre distance of `min_spacing` diameters (Sec. 3),
+    measured periodically across the top/bottom walls."""
+    nx, ny = int(length), int(width)
+    region = nx - strip
+    ncav = int(round(cavity_count(phi, float(region), float(ny), float(d_c))))
+    R = 0.5 * d_c
+    dmin = min_spacing * d_c
+    rng = np.random.default_rng(seed)
+    xs = np.empty(ncav)
+    ys = np.empty(ncav)
+    k = draws = 0
+    while k < ncav:
+        draws += 1
+        if draws > max_draws:
+            raise RuntimeError(f"cavity placement failed ({k}/{ncav})")
+        x = rng.uniform(strip + R + 2.0, nx - R - 2.0)
+        y = rng.uniform(0.0, ny)
+        if k:
+            ddy = np.abs(ys[:k] - y)
+            ddy = np.minimum(ddy, ny - ddy)
+            if np.any((xs[:k] - x) ** 2 + ddy ** 2 < dmin * dmin):
+                continue
+        xs[k], ys[k] = x, y
+        k += 1
+    prim = _blank(nx, ny)
+    rho1, u1, S = stiffened_gas_shock(p_shock)
+    prim[2, :, :strip] = rho1
+    prim[3, :, :strip] = u1
+    prim[5, :, :strip] = p_shock
+    for x, y in zip(xs, ys):
+        _paint_bubble_periodic_y(prim[0], x, y, R)
+    cen = np.stack([xs, ys, np.full(ncav, R)], axis=1)
+    return Scenario("random_cavities", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                    bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
+                    meta=dict(seed=seed, ncavities=ncav, porosity_target=phi, p_shock=p_shock,
+                              shock_speed=S, bubbles=cen, nbubbles=ncav))
+
+
 def uniform_state(nx: int, ny: int, dx: float = 1.0e-3, z1: float = Z_EPS,
                   rho1: float = RHO_AIR, rho2: float = RHO_WATER, u: float = 0.0,
                   v: float = 0.0, p: float = P_AMBIENT) -> np.ndarray:

@@ -196,6 +196,71 @@ def test_fp64_roofline_8192_sampled(start):
     assert_bitwise(got, exp, "sampled 8192^2")
 
 
+def test_random_field_4096_full_run():
+    """4096 x 2048 random bubble field, its full 5000 steps: the FP64 run's last
+    step is checked against the oracle on sampled cells; the FP32-bulk and FP32
+    runs against FP64 by relative L1 (density <= 1e-4, pressure <= 1e-3)."""
+    sc = S.random_field_4096()
+    steps = sc.steps
+    say(f"case: random field 4096x2048, {steps} steps, three precisions")
+    fields = {}
+    for prec in ("fp64", "fp32_fp64acc", "fp32"):
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            if prec == "fp64":
+                s.run_steps(steps - 1)
+                U0 = s.read_conserved()
+                t0, n0, _ = s.time()
+                s.run_steps(1)
+                U1 = s.read_conserved()
+                t1, _, dt = s.time()
+            else:
+                s.run_steps(steps)
+            fields[prec] = {k: s.read_field(k) for k in ("rho", "p")}
+            say(prec, "t =", s.time()[0])
+    o = oracle_of(sc)
+    o.U[...] = U0
+    o.t, o.step = t0, n0
+    dto, tno = o.cfl_dt()
+    assert dt == dto and t1 == tno
+    rng = np.random.default_rng(9)
+    cells = rng.integers(0, sc.nx * sc.ny, 4000)
+    assert_bitwise(U1.reshape(6, -1)[:, cells], o.step_cells(U0, n0, dto, cells),
+                   "sampled 4096x2048 step 5000")
+    for prec in ("fp32_fp64acc", "fp32"):
+        e_rho = rel_l1(fields[prec]["rho"], fields["fp64"]["rho"])
+        e_p = rel_l1(fields[prec]["p"], fields["fp64"]["p"])
+        say(f"{prec}: rel L1 rho {e_rho:.3e}  p {e_p:.3e}")
+        assert e_rho <= 1e-4 and e_p <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["regular_array", "random_cavities"])
+def test_paper_shaped_fields_sampled(which):
+    """The paper's own workload shapes (Sec. 2.4, App. A) at full size:
+    24000 x 313 regular array and 24000 x 2000 random field (100 cells per
+    cavity diameter, periodic top/bottom).  After 3 steps, step 4 (y-x order)
+    is checked against the oracle on sampled cells incl. the periodic seams
+    and the ragged last strip."""
+    sc = getattr(S, which)()
+    say(f"case: {which} {sc.nx}x{sc.ny} sampled, periodic y")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(3)
+        U0 = s.read_conserved()
+        t0, n0, _ = s.time()
+        s.run_steps(1)
+        U1 = s.read_conserved()
+        _, _, dt = s.time()
+    o = oracle_of(sc)
+    o.U[...] = U0
+    o.t, o.step = t0, n0
+    dto, _ = o.cfl_dt()
+    assert dt == dto
+    rng = np.random.default_rng(4)
+    ii = list(rng.integers(0, sc.nx, 3000)) + [0, 1, sc.nx - 2, sc.nx - 1, 499, 500, 501] * 4
+    jj = list(rng.integers(0, sc.ny, 3000)) + [0, 1, sc.ny - 2, sc.ny - 1] * 7
+    cells = np.array(jj, dtype=np.int64) * sc.nx + np.array(ii, dtype=np.int64)
+    assert_bitwise(U1.reshape(6, -1)[:, cells], o.step_cells(U0, n0, dto, cells), which)
+
+
 # ------------------------------------------------------------ FP32 modes ----
 def test_reduced_precision_modes_within_tolerance():
     """Single bubble 1024x512, 2000 steps: FP32-bulk/FP64-accumulate and pure

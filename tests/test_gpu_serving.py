@@ -116,3 +116,18 @@ def test_serve_poisson_replay():
         res = serve.serve(srv, reqs, arr, 60)
     assert np.all(res["latencies"] > 0) and res["p99_s"] >= res["p50_s"]
     assert res["stats"]["completed"] == 16
+
+
+def test_serving_workload_sizes_alone_equals_in_mix():
+    """Requests of the serving workload itself (128^2, 256^2, 512^2 grids,
+    0.5-2 GPa shocks), FP32-bulk mode, batched vs alone."""
+    reqs = S.serving_workload(6, steps=0)
+    nsteps = 80
+    say(f"case: serving sizes {[r.nx for r in reqs]}, {nsteps} steps")
+    with serve.Server(4 << 30, max_slots=4, precision="fp32_fp64acc") as srv:
+        tks = [srv.submit(sc, nsteps) for sc in reqs]
+        srv.drain()
+        got = [srv.result(tk) for tk in tks]
+    for sc, (Ub, tb, nb) in zip(reqs, got):
+        U, t, n = serve.solve_alone(sc, nsteps)
+        assert nb == n == nsteps and tb == t and np.array_equal(U, Ub)
