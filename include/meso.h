@@ -168,6 +168,26 @@ int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count);
 /* Time, completed step count and the last time step.  Synchronises. */
 int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt);
 
+/* Diagnostics of the current state (synchronise; the closure is evaluated in
+ * FP64 on the stored values; sums run in a fixed order, so results do not
+ * depend on the launch geometry).
+ *
+ * Transverse averages of Sec. 4.2, one value per column (nx each):
+ *   p_bar = (1/W) int p dy,  rho_bar = (1/W) int rho dy,
+ *   u_bar = (1/(W rho_bar)) int rho u dy (density-weighted). */
+int32_t mf_y_averages(mf_solver *s, double *p_bar, double *rho_bar, double *u_bar, size_t nx);
+
+/* Domain integrals over the grid (cell area dx*dy), count must be 6:
+ *   z1 rho1, z2 rho2, rho u, rho v, rho E and the gas volume z1. */
+int32_t mf_integrals(mf_solver *s, double *out, size_t count);
+
+/* Mass-weighted probability density on log-spaced bins (Sec. 4.5): bin k
+ * covers 10^(lo + k dn) <= v < 10^(lo + (k+1) dn) of the field v (MF_P or
+ * MF_RHO), collects the liquid mass z2 rho2 dx dy of its cells, and
+ * f_out[k] = m_k / (m_ref dn).  1 <= nbins <= 1024, dn > 0, m_ref > 0. */
+int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
+                         double m_ref, double *f_out);
+
 /* Kernel timing: when enabled, every step kernel launch is bracketed by HIP
  * events on the solver's stream.  mf_kernel_time synchronises and returns the
  * summed duration (ms) and launch count of the state-update kernels since

@@ -81,6 +81,11 @@ def _load():
         lib.or_unit_hllc.argtypes = [P, D, D, D]
         lib.or_unit_sweep_line.argtypes = [P, C.c_int64, D, D, C.c_double]
         lib.or_num_threads.restype = C.c_int32
+        lib.or_y_averages.argtypes = [P, D, D, D, D]
+        lib.or_integrals.argtypes = [P, D, D]
+        lib.or_log_edges.argtypes = [C.c_double, C.c_double, C.c_int32, D]
+        lib.or_log_histogram.argtypes = [P, D, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                         C.c_double, D]
         _lib = lib
     return _lib
 
@@ -177,6 +182,24 @@ class Oracle:
         self.last_dt = ldt.value
         return int(n)
 
+    # -- diagnostics (Sec. 4.2, Sec. 4.5) ---------------------------------
+    def y_averages(self):
+        nx = self.prob.nx
+        p, r, u = (np.empty(nx) for _ in range(3))
+        _load().or_y_averages(C.byref(self._p), _dp(self.U), _dp(p), _dp(r), _dp(u))
+        return p, r, u
+
+    def integrals(self) -> np.ndarray:
+        out = np.empty(6)
+        _load().or_integrals(C.byref(self._p), _dp(self.U), _dp(out))
+        return out
+
+    def log_histogram(self, field: int, lo: float, dn: float, nbins: int, m_ref: float):
+        f = np.empty(nbins)
+        _load().or_log_histogram(C.byref(self._p), _dp(self.U), field, lo, dn, nbins, m_ref,
+                                 _dp(f))
+        return f
+
     def step_cells(self, U: np.ndarray, step: int, dt: float, cells: np.ndarray) -> np.ndarray:
         """Post-step state at flat cell indices j*nx+i, from pre-step state U."""
         U = np.ascontiguousarray(U, dtype=np.float64)
@@ -223,6 +246,12 @@ def unit_sweep_line(prob: Problem, q: np.ndarray, lam: float) -> np.ndarray:
     out = np.empty_like(q)
     _load().or_unit_sweep_line(C.byref(prob._c()), q.shape[1], _dp(q), _dp(out), lam)
     return out
+
+
+def log_edges(lo: float, dn: float, nbins: int) -> np.ndarray:
+    e = np.empty(nbins + 1)
+    _load().or_log_edges(lo, dn, nbins, _dp(e))
+    return e
 
 
 def num_threads() -> int:

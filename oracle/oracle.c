@@ -613,3 +613,101 @@ int32_t or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Diagnostics (Sec. 4.2 transverse averages; Sec. 4.5 mass-weighted PDFs).  */
+
+/* Pressure, density and x-momentum of a cell through the closure. */
+static void cell_prim(const mixc *m, const double *U, long N, long k, double *p, double *rho,
+                      double *mu)
+{
+    double q[NV], w[NV], r, rc2;
+    int c;
+    for (c = 0; c < NV; ++c) q[c] = U[c * N + k];
+    cons_to_prim(m, q, w, &r, &rc2);
+    *p = w[4];
+    *rho = q[0] + q[1];
+    *mu = q[2];
+}
+
+/* Transverse averages over y of each column i (sums taken in increasing j):
+ *   pbar(x) = (1/ny) sum_j p,  rhobar(x) = (1/ny) sum_j rho,
+ *   ubar(x) = sum_j rho u / sum_j rho  (density-weighted velocity).          */
+void or_y_averages(const or_problem *P, const double *U, double *pbar, double *rhobar,
+                   double *ubar)
+{
+    mixc m = mix_constants(P);
+    long nx = P->nx, ny = P->ny, N = nx * ny, i, j;
+    for (i = 0; i < nx; ++i) {
+        double sp = 0.0, sr = 0.0, sm = 0.0;
+        for (j = 0; j < ny; ++j) {
+            double p, rho, mu;
+            cell_prim(&m, U, N, j * nx + i, &p, &rho, &mu);
+            sp = sp + p;
+            sr = sr + rho;
+            sm = sm + mu;
+        }
+        pbar[i] = sp / (double)ny;
+        rhobar[i] = sr / (double)ny;
+        ubar[i] = sm / sr;
+    }
+}
+
+/* Domain integrals (cell area dx*dy): z1 rho1, z2 rho2, rho u, rho v, rho E,
+ * air volume z1.  Each is (sum over i of (sum over j of q)) * area, both sums
+ * in increasing index order.                                                */
+void or_integrals(const or_problem *P, const double *U, double out[6])
+{
+    long nx = P->nx, ny = P->ny, N = nx * ny, i, j;
+    int c;
+    double area = P->dx * P->dy;
+    for (c = 0; c < 6; ++c) {
+        double tot = 0.0;
+        for (i = 0; i < nx; ++i) {
+            double s = 0.0;
+            for (j = 0; j < ny; ++j) s = s + U[c * N + j * nx + i];
+            tot = tot + s;
+        }
+        out[c] = tot * area;
+    }
+}
+
+/* Bin edges 10^(lo + k dn), k = 0..nbins. */
+void or_log_edges(double lo, double dn, int32_t nbins, double *edges)
+{
+    int32_t k;
+    for (k = 0; k <= nbins; ++k) edges[k] = pow(10.0, lo + (double)k * dn);
+}
+
+/* Mass-weighted histogram of pressure (field 9) or density (field 6) over
+ * the log-spaced bins: m_k = sum of z2 rho2 dx dy over cells with
+ * edges[k] <= v < edges[k+1];  f_k = m_k / (m_ref dn).                       */
+void or_log_histogram(const or_problem *P, const double *U, int32_t field, double lo, double dn,
+                      int32_t nbins, double m_ref, double *f)
+{
+    mixc m = mix_constants(P);
+    long N = (long)P->nx * P->ny, k;
+    double area = P->dx * P->dy;
+    double *edges = (double *)malloc((size_t)(nbins + 1) * sizeof(double));
+    int32_t b;
+    or_log_edges(lo, dn, nbins, edges);
+    for (b = 0; b < nbins; ++b) f[b] = 0.0;
+    for (k = 0; k < N; ++k) {
+        double p, rho, mu, v;
+        int32_t a, z;
+        cell_prim(&m, U, N, k, &p, &rho, &mu);
+        v = (field == 6) ? rho : p;
+        if (!(v >= edges[0]) || !(v < edges[nbins])) continue;
+        /* largest a with edges[a] <= v */
+        a = 0;
+        z = nbins;
+        while (z - a > 1) {
+            int32_t h = (a + z) / 2;
+            if (edges[h] <= v) a = h;
+            else z = h;
+        }
+        f[a] += U[N + k] * area;
+    }
+    for (b = 0; b < nbins; ++b) f[b] = f[b] / (m_ref * dn);
+    free(edges);
+}

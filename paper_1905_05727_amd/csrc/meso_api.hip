@@ -361,6 +361,83 @@ int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count) {
     return MF_OK;
 }
 
+// Column sums of the current state into a temporary device array (9 * nx).
+static int32_t column_pass(mf_solver *s, double **cols_out) {
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (c.err) return MF_E_NONFINITE_STATE;
+    double *cols = nullptr;
+    if (hipMalloc(&cols, sizeof(double) * (9 * (size_t)s->grid.nx + 8)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MF_E_OUT_OF_MEMORY;
+    }
+    hipError_t e = meso::launch_columns(s->d, s->opt.precision, state_index(s, c.step), cols,
+                                        s->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(cols);
+        return MF_E_DEVICE;
+    }
+    *cols_out = cols;
+    return MF_OK;
+}
+
+int32_t mf_y_averages(mf_solver *s, double *p_bar, double *rho_bar, double *u_bar, size_t nx) {
+    if (!s || !p_bar || !rho_bar || !u_bar || nx != (size_t)s->grid.nx) return MF_E_INVALID_ARG;
+    double *cols = nullptr;
+    int32_t st = column_pass(s, &cols);
+    if (st != MF_OK) return st;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(p_bar, cols, nx * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(rho_bar, cols + nx, nx * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(u_bar, cols + 2 * nx, nx * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(cols);
+    return dev_err(e);
+}
+
+int32_t mf_integrals(mf_solver *s, double *out, size_t count) {
+    if (!s || !out || count != 6) return MF_E_INVALID_ARG;
+    double *cols = nullptr;
+    int32_t st = column_pass(s, &cols);
+    if (st != MF_OK) return st;
+    double *res = cols + 9 * (size_t)s->grid.nx;
+    hipError_t e = meso::launch_integrals(s->d, cols, res, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(out, res, 6 * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(cols);
+    return dev_err(e);
+}
+
+int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
+                         double m_ref, double *f_out) {
+    if (!s || !f_out || (field != MF_P && field != MF_RHO) || nbins < 1 || nbins > 1024 ||
+        !(dn > 0.0) || !isfinite(lo) || !isfinite(dn) || !(m_ref > 0.0))
+        return MF_E_INVALID_ARG;
+    Control c;
+    int32_t st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (c.err) return MF_E_NONFINITE_STATE;
+    std::vector<double> edges(nbins + 1);
+    for (int32_t k = 0; k <= nbins; ++k) edges[k] = pow(10.0, lo + (double)k * dn);
+    double *dev = nullptr;
+    if (hipMalloc(&dev, sizeof(double) * (2 * (size_t)nbins + 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MF_E_OUT_OF_MEMORY;
+    }
+    double *d_edges = dev, *d_bins = dev + nbins + 1;
+    hipError_t e = hipMemcpy(d_edges, edges.data(), sizeof(double) * (nbins + 1),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = meso::launch_histogram(s->d, s->opt.precision, state_index(s, c.step), field, d_edges,
+                                   nbins, m_ref, dn, d_bins, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(f_out, d_bins, sizeof(double) * nbins, hipMemcpyDeviceToHost);
+    (void)hipFree(dev);
+    return dev_err(e);
+}
+
 int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt) {
     if (!s) return MF_E_INVALID_ARG;
     Control c;

@@ -82,6 +82,12 @@ hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pas
                        hipStream_t st);
 hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double *out,
                              hipStream_t st);
+// Diagnostics: out = 9 * nx doubles (pbar, rhobar, ubar, 6 column sums);
+// integrals from those column sums; a mass-weighted log-binned histogram.
+hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStream_t st);
+hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipStream_t st);
+hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const double *edges,
+                            int nbins, double m_ref, double dn, double *bins, hipStream_t st);
 // Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
 // into descs, strip, segment, unused).
 hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);

@@ -193,6 +193,102 @@ __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
 }
 
 // ------------------------------------------------------------------------
+// Diagnostics (Sec. 4.2 transverse averages, Sec. 4.5 mass-weighted PDFs).
+// The closure is evaluated in FP64 on the stored state; every sum runs in a
+// fixed order (increasing j inside a column, then increasing i), so the
+// results do not depend on the launch geometry.
+
+// One thread per column: out[0..2][i] = pbar, rhobar, density-weighted ubar;
+// out[3+c][i] = sum over the column of conserved component c.
+template <class S>
+__global__ void column_kernel(Desc d, int src_idx, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nx) return;
+    const S *src = (const S *)d.buf[src_idx];
+    const Mix<double> m = mix_of<double>(d);
+    double sp = 0.0, sr = 0.0, sm = 0.0, sc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < d.ny; ++j) {
+        const long long o = (long long)j * d.pitch + i;
+        double q[6], w[6], r, rc2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = (double)src[c * d.plane + o];
+        cons_to_prim<double, false>(m, q, w, r, rc2);
+        sp = sp + w[4];
+        sr = sr + (q[0] + q[1]);
+        sm = sm + q[2];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sc[c] = sc[c] + q[c];
+    }
+    const long long n = d.nx;
+    out[i] = sp / (double)d.ny;
+    out[n + i] = sr / (double)d.ny;
+    out[2 * n + i] = sm / sr;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[(3 + c) * n + i] = sc[c];
+}
+
+// Domain integrals from the column sums (one thread, increasing i).
+__global__ void integrals_kernel(int nx, double area, const double *cols, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int c = 0; c < 6; ++c) {
+        double tot = 0.0;
+        const double *s = cols + (long long)(3 + c) * nx;
+        for (int i = 0; i < nx; ++i) tot = tot + s[i];
+        out[c] = tot * area;
+    }
+}
+
+constexpr int kMaxBins = 1024;
+
+// Mass-weighted histogram over log-spaced bins: bin a (edges[a] <= v <
+// edges[a+1], v = pressure or density) collects z2 rho2 * area.  Per-workgroup
+// LDS histograms, then one global atomic add per non-empty bin.
+template <class S>
+__global__ __launch_bounds__(kThreads) void histo_kernel(Desc d, int src_idx, int field,
+                                                         const double *edges, int nbins,
+                                                         double area, double *bins) {
+    __shared__ double h[kMaxBins];
+    __shared__ double e[kMaxBins + 1];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) h[b] = 0.0;
+    for (int b = threadIdx.x; b <= nbins; b += blockDim.x) e[b] = edges[b];
+    __syncthreads();
+    const S *src = (const S *)d.buf[src_idx];
+    const Mix<double> m = mix_of<double>(d);
+    const long long N = (long long)d.nx * d.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+        const long long o = (long long)j * d.pitch + i;
+        double q[6], w[6], r, rc2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) q[c] = (double)src[c * d.plane + o];
+        cons_to_prim<double, false>(m, q, w, r, rc2);
+        const double v = (field == 6) ? (q[0] + q[1]) : w[4];
+        if (!(v >= e[0]) || !(v < e[nbins])) continue;
+        int a = 0, z = nbins;
+        while (z - a > 1) {
+            const int hh = (a + z) / 2;
+            if (e[hh] <= v) a = hh;
+            else z = hh;
+        }
+        atomicAdd(&h[a], q[1] * area);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (h[b] != 0.0) atomicAdd(&bins[b], h[b]);
+}
+
+__global__ void fill_kernel(double *x, int n, double v) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = v;
+}
+
+__global__ void scale_kernel(double *x, int n, double s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = x[k] / s;
+}
+
+// ------------------------------------------------------------------------
 // Launchers.
 static int grid_for(long long n) {
     long long g = (n + kThreads - 1) / kThreads;
@@ -300,6 +396,38 @@ hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double
     else
         hipLaunchKernelGGL(read_field_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, src,
                            field, out);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStream_t st) {
+    const int g = (d.nx + 255) / 256;
+    if (prec == kP32)
+        hipLaunchKernelGGL(column_kernel<float>, dim3(g), dim3(256), 0, st, d, src, out);
+    else
+        hipLaunchKernelGGL(column_kernel<double>, dim3(g), dim3(256), 0, st, d, src, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(integrals_kernel, dim3(1), dim3(64), 0, st, d.nx, d.dx * d.dy, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const double *edges,
+                            int nbins, double m_ref, double dn, double *bins, hipStream_t st) {
+    if (nbins < 1 || nbins > kMaxBins) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fill_kernel, dim3((nbins + 255) / 256), dim3(256), 0, st, bins, nbins, 0.0);
+    const int g = grid_for((long long)d.nx * d.ny);
+    const double area = d.dx * d.dy;
+    if (prec == kP32)
+        hipLaunchKernelGGL(histo_kernel<float>, dim3(g), dim3(kThreads), 0, st, d, src, field,
+                           edges, nbins, area, bins);
+    else
+        hipLaunchKernelGGL(histo_kernel<double>, dim3(g), dim3(kThreads), 0, st, d, src, field,
+                           edges, nbins, area, bins);
+    hipLaunchKernelGGL(scale_kernel, dim3((nbins + 255) / 256), dim3(256), 0, st, bins, nbins,
+                       m_ref * dn);
     return hipGetLastError();
 }
 

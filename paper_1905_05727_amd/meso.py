@@ -28,7 +28,8 @@ FIELDS = {"z1rho1": 0, "z2rho2": 1, "rhou": 2, "rhov": 3, "rhoE": 4, "z1": 5,
 EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conserved",
            "mf_set_time", "mf_step", "mf_run_steps", "mf_run_to_time", "mf_sync",
            "mf_read_field", "mf_read_conserved", "mf_get_time", "mf_enable_timing",
-           "mf_kernel_time", "mf_launch_info", "mf_destroy", "mf_status_str", "mf_version",
+           "mf_kernel_time", "mf_launch_info", "mf_y_averages", "mf_integrals",
+           "mf_log_histogram", "mf_destroy", "mf_status_str", "mf_version",
            "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
            "mf_server_poll", "mf_server_result", "mf_server_drain", "mf_server_get_stats",
            "mf_server_destroy"]
@@ -98,6 +99,10 @@ def load_library():
         "mf_enable_timing": (C.c_int32, [P, C.c_int32]),
         "mf_kernel_time": (C.c_int32, [P, D, I64]),
         "mf_launch_info": (C.c_int32, [P, I64, I32, I32, I32]),
+        "mf_y_averages": (C.c_int32, [P, D, D, D, C.c_size_t]),
+        "mf_integrals": (C.c_int32, [P, D, C.c_size_t]),
+        "mf_log_histogram": (C.c_int32, [P, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                         C.c_double, D]),
         "mf_destroy": (C.c_int32, [P]),
         "mf_status_str": (C.c_char_p, [C.c_int32]),
         "mf_server_request_bytes": (C.c_size_t, [C.POINTER(Grid), C.c_int32]),
@@ -229,6 +234,27 @@ class Solver:
         dt = C.c_double()
         _chk("mf_get_time", self._lib.mf_get_time(self._h, C.byref(t), C.byref(n), C.byref(dt)))
         return t.value, n.value, dt.value
+
+    # --------------------------------------------------------- diagnostics
+    def y_averages(self):
+        """(p_bar, rho_bar, u_bar) over y, one value per column (Sec. 4.2)."""
+        p, r, u = (np.empty(self.nx) for _ in range(3))
+        _chk("mf_y_averages", self._lib.mf_y_averages(self._h, _dptr(p), _dptr(r), _dptr(u),
+                                                       self.nx))
+        return p, r, u
+
+    def integrals(self) -> np.ndarray:
+        out = np.empty(6)
+        _chk("mf_integrals", self._lib.mf_integrals(self._h, _dptr(out), 6))
+        return out
+
+    def log_histogram(self, field, lo: float, dn: float, nbins: int, m_ref: float):
+        f = FIELDS[field] if isinstance(field, str) else int(field)
+        out = np.empty(int(nbins))
+        _chk("mf_log_histogram", self._lib.mf_log_histogram(self._h, f, float(lo), float(dn),
+                                                             int(nbins), float(m_ref),
+                                                             _dptr(out)))
+        return out
 
     # -------------------------------------------------------------- timing
     def enable_timing(self, on: bool = True) -> None:

@@ -349,3 +349,29 @@ def test_nonfinite_state_is_reported():
             s.run_steps(2)
             s.sync()
             assert s.time()[1] == 2
+
+
+# ------------------------------------------------------------ diagnostics ----
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_diagnostics_match_oracle(prec):
+    """Transverse averages, integrals (fixed summation order: bitwise) and the
+    mass-weighted log-binned pressure PDF (bin decisions exact, bin masses to
+    1e-12) of the stored state, against the oracle on the same values."""
+    sc = bubble(300, 140)
+    say(f"case: diagnostics 300x140 {prec}")
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(60)
+        U = s.read_conserved()
+        pb, rb, ub = s.y_averages()
+        integ = s.integrals()
+        area = sc.dx * sc.dy
+        m_ref = float(U[1].sum() * area)
+        f = s.log_histogram("p", 4.0, 0.02, 300, m_ref)
+    o = oracle_of(sc)
+    o.U[...] = U
+    po, ro, uo = o.y_averages()
+    assert_bitwise(np.stack([pb, rb, ub]), np.stack([po, ro, uo]), "y averages")
+    assert_bitwise(integ, o.integrals(), "integrals")
+    fo = o.log_histogram(9, 4.0, 0.02, 300, m_ref)
+    assert np.array_equal(f > 0, fo > 0)
+    np.testing.assert_allclose(f, fo, rtol=1e-12, atol=0)
