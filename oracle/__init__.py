@@ -48,7 +48,9 @@ class _Problem(C.Structure):
                 ("bc_xlo", C.c_int32), ("bc_xhi", C.c_int32), ("bc_ylo", C.c_int32),
                 ("bc_yhi", C.c_int32), ("gamma1", C.c_double), ("pinf1", C.c_double),
                 ("gamma2", C.c_double), ("pinf2", C.c_double), ("cfl", C.c_double),
-                ("zeps", C.c_double), ("limiter", C.c_int32), ("pad_", C.c_int32)]
+                ("zeps", C.c_double), ("limiter", C.c_int32), ("eos2", C.c_int32),
+                ("cc_gamma0", C.c_double), ("cc_A", C.c_double), ("cc_B", C.c_double),
+                ("cc_C", C.c_double), ("cc_D", C.c_double), ("cc_rho0", C.c_double)]
 
 
 _lib = None
@@ -82,6 +84,9 @@ def _load():
         lib.or_unit_sweep_line.argtypes = [P, C.c_int64, D, D, C.c_double]
         lib.or_num_threads.restype = C.c_int32
         lib.or_y_averages.argtypes = [P, D, D, D, D]
+        lib.or_liquid_temperature.argtypes = [P, C.c_double, C.c_double, C.c_double]
+        lib.or_liquid_temperature.restype = C.c_double
+        lib.or_unit_cc_reference.argtypes = [P, C.c_double, D]
         lib.or_integrals.argtypes = [P, D, D]
         lib.or_log_edges.argtypes = [C.c_double, C.c_double, C.c_int32, D]
         lib.or_log_histogram.argtypes = [P, D, C.c_int32, C.c_double, C.c_double, C.c_int32,
@@ -116,11 +121,14 @@ class Problem:
     bc_xhi: int = TRANSMISSIVE
     bc_ylo: int = TRANSMISSIVE
     bc_yhi: int = TRANSMISSIVE
+    # liquid equation of state: 0 stiffened gas (gamma2, pinf2), 1 Cochran-Chan
+    eos2: int = 0
+    cc: tuple = (1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0)   # Gamma0, A, B, C, D, rho0
 
     def _c(self) -> _Problem:
         return _Problem(self.nx, self.ny, self.dx, self.dy, self.bc_xlo, self.bc_xhi,
                         self.bc_ylo, self.bc_yhi, self.gamma1, self.pinf1, self.gamma2,
-                        self.pinf2, self.cfl, self.zeps, self.limiter, 0)
+                        self.pinf2, self.cfl, self.zeps, self.limiter, self.eos2, *self.cc)
 
 
 class Oracle:
@@ -246,6 +254,17 @@ def unit_sweep_line(prob: Problem, q: np.ndarray, lam: float) -> np.ndarray:
     out = np.empty_like(q)
     _load().or_unit_sweep_line(C.byref(prob._c()), q.shape[1], _dp(q), _dp(out), lam)
     return out
+
+
+def cc_reference(prob: Problem, rho: float):
+    """(p_ref, e_ref, rho dp_ref/drho) of the Cochran-Chan liquid at rho."""
+    out = np.empty(3)
+    _load().or_unit_cc_reference(C.byref(prob._c()), rho, _dp(out))
+    return out
+
+
+def liquid_temperature(prob: Problem, rho2: float, p: float, cv2: float = 1714.0) -> float:
+    return _load().or_liquid_temperature(C.byref(prob._c()), rho2, p, cv2)
 
 
 def log_edges(lo: float, dn: float, nbins: int) -> np.ndarray:

@@ -45,22 +45,70 @@ typedef struct {
     double gamma1, pinf1, gamma2, pinf2;    /* phase 1 = air, phase 2 = liquid */
     double cfl, zeps;
     int32_t limiter;                        /* 0 van Leer, 1 minmod */
-    int32_t pad_;
+    int32_t eos2;                           /* liquid: 0 stiffened gas, 1 Cochran-Chan */
+    double cc_gamma0, cc_A, cc_B, cc_C, cc_D, cc_rho0;   /* Eqs. (2)-(4), Table 1 */
 } or_problem;
 
-/* Stiffened-gas mixture constants: rho e = p * xi + eta with
- * xi = sum z_k g_k, eta = sum z_k h_k, g_k = 1/(gamma_k - 1),
- * h_k = gamma_k p_inf_k / (gamma_k - 1)   (Eq. (2) with constant references). */
-typedef struct { double g1, g2, h1, h2; } mixc;
+/* Mixture constants.  Every phase is written in the Mie-Grueneisen form of
+ * Eq. (2), so that rho_k e_k = phi_k(rho_k) + p / Gamma_k with
+ * phi_k = rho_k e_ref,k - p_ref,k / Gamma_k, and the pressure-equilibrium
+ * closure of Sec. 2.1 becomes  rho e = p xi + eta,  xi = sum z_k / Gamma_k,
+ * eta = sum z_k phi_k(rho_k).
+ * Stiffened gas: Gamma = gamma - 1, phi = gamma p_inf / (gamma - 1) =: h,
+ * constant.  Cochran-Chan (Eqs. (3)-(4)): phi depends on rho_2.          */
+typedef struct {
+    double g1, g2, h1, h2;
+    int eos2;
+    double A, B, C, D, rho0, iG, kA, kB;
+} mixc;
 
 static mixc mix_constants(const or_problem *P)
 {
     mixc m;
     m.g1 = 1.0 / (P->gamma1 - 1.0);
-    m.g2 = 1.0 / (P->gamma2 - 1.0);
     m.h1 = (P->gamma1 * P->pinf1) * m.g1;
-    m.h2 = (P->gamma2 * P->pinf2) * m.g2;
+    m.eos2 = P->eos2;
+    if (P->eos2 == 1) {
+        m.iG = 1.0 / P->cc_gamma0;
+        m.g2 = m.iG;
+        m.h2 = 0.0;
+        m.A = P->cc_A;
+        m.B = P->cc_B;
+        m.C = P->cc_C;
+        m.D = P->cc_D;
+        m.rho0 = P->cc_rho0;
+        m.kA = -P->cc_A / (P->cc_rho0 * (1.0 - P->cc_C));
+        m.kB = P->cc_B / (P->cc_rho0 * (1.0 - P->cc_D));
+    } else {
+        m.g2 = 1.0 / (P->gamma2 - 1.0);
+        m.h2 = (P->gamma2 * P->pinf2) * m.g2;
+        m.iG = m.A = m.B = m.C = m.D = m.rho0 = m.kA = m.kB = 0.0;
+    }
     return m;
+}
+
+/* Cochran-Chan reference curves at liquid density rho (Eqs. (3)-(4)):
+ * p_ref, e_ref and rho dp_ref/drho, with v = rho0 / rho.                    */
+static void cc_reference(const mixc *m, double rho, double *pref, double *eref, double *rdpref)
+{
+    double v = m->rho0 / rho;
+    double vc = pow(v, -m->C), vd = pow(v, -m->D);
+    *pref = m->A * vc - m->B * vd;
+    *eref = m->kA * (v * vc - 1.0) + m->kB * (v * vd - 1.0);
+    *rdpref = (m->A * m->C) * vc - (m->B * m->D) * vd;
+}
+
+/* Liquid contributions z2 phi2(rho2) to eta and z2 rho2 phi2'(rho2) to psi,
+ * the term the density dependence of phi adds to the frozen sound speed:
+ * rho c^2 = (p (1 + xi) + eta - psi) / xi.   rho2 = a2 / z2.              */
+static void liquid_terms(const mixc *m, double a2, double z2, double *eta2, double *psi2)
+{
+    double rho2 = a2 / z2, pref, eref, rdpref, phi, rphi;
+    cc_reference(m, rho2, &pref, &eref, &rdpref);
+    phi = rho2 * eref - pref * m->iG;
+    rphi = (rho2 * eref + pref) - rdpref * m->iG;
+    *eta2 = z2 * phi;
+    *psi2 = z2 * rphi;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -81,10 +129,20 @@ static void cons_to_prim(const mixc *m, const double q[NV], double w[NV],
     double z = q[5];
     double z2 = 1.0 - z;
     double xi = z * m->g1 + z2 * m->g2;
-    double eta = z * m->h1 + z2 * m->h2;
-    double ixi = 1.0 / xi;
-    double p = (rhoe - eta) * ixi;
-    double rc2 = (p * (1.0 + xi) + eta) * ixi;
+    double eta, ixi, p, rc2;
+    if (m->eos2 == 1) {
+        double eta2, psi2;
+        liquid_terms(m, q[1], z2, &eta2, &psi2);
+        eta = z * m->h1 + eta2;
+        ixi = 1.0 / xi;
+        p = (rhoe - eta) * ixi;
+        rc2 = ((p * (1.0 + xi) + eta) - psi2) * ixi;
+    } else {
+        eta = z * m->h1 + z2 * m->h2;
+        ixi = 1.0 / xi;
+        p = (rhoe - eta) * ixi;
+        rc2 = (p * (1.0 + xi) + eta) * ixi;
+    }
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
     *r_out = r;
     *rc2_out = rc2;
@@ -149,8 +207,16 @@ static void side_eval(const mixc *m, const double w[NV], side_t *s)
     double un = w[2], ut = w[3], p = w[4], z = w[5];
     double z2 = 1.0 - z;
     double xi = z * m->g1 + z2 * m->g2;
-    double eta = z * m->h1 + z2 * m->h2;
-    double c = sqrt((p * (1.0 + xi) + eta) / (xi * rho));
+    double eta, c;
+    if (m->eos2 == 1) {
+        double eta2, psi2;
+        liquid_terms(m, w[1], z2, &eta2, &psi2);
+        eta = z * m->h1 + eta2;
+        c = sqrt(((p * (1.0 + xi) + eta) - psi2) / (xi * rho));
+    } else {
+        eta = z * m->h1 + z2 * m->h2;
+        c = sqrt((p * (1.0 + xi) + eta) / (xi * rho));
+    }
     double E = (p * xi + eta) + 0.5 * (rho * (un * un + ut * ut));
     double mn = rho * un;
     s->rho = rho; s->un = un; s->ut = ut; s->p = p; s->z = z; s->c = c; s->E = E;
@@ -369,7 +435,14 @@ void or_prim_to_cons(const or_problem *P, const double *prim, double *U)
         double a1 = z * r1, a2 = z2 * r2;
         double rho = a1 + a2;
         double xi = z * m.g1 + z2 * m.g2;
-        double eta = z * m.h1 + z2 * m.h2;
+        double eta;
+        if (m.eos2 == 1) {
+            double eta2, psi2;
+            liquid_terms(&m, a2, z2, &eta2, &psi2);
+            eta = z * m.h1 + eta2;
+        } else {
+            eta = z * m.h1 + z2 * m.h2;
+        }
         U[k] = a1;
         U[N + k] = a2;
         U[2 * N + k] = rho * u;
@@ -564,6 +637,23 @@ void or_step_cells(const or_problem *P, const double *U, int64_t step, double dt
         }
         for (c = 0; c < NV; ++c) out[c * ncells + s] = qo[c];
     }
+}
+
+/* Temperature of the liquid from the linearisation about its reference curve
+ * (Eq. (5) with T_ref,2 = 0, constant c_v,2 and Gamma_0,2):
+ *   T2 = (p - p_ref,2(rho2)) / (rho2 Gamma_0,2 c_v,2).                      */
+double or_liquid_temperature(const or_problem *P, double rho2, double p, double cv2)
+{
+    mixc m = mix_constants(P);
+    double pref, eref, rdpref;
+    cc_reference(&m, rho2, &pref, &eref, &rdpref);
+    return (p - pref) / (rho2 * P->cc_gamma0 * cv2);
+}
+
+void or_unit_cc_reference(const or_problem *P, double rho, double out[3])
+{
+    mixc m = mix_constants(P);
+    cc_reference(&m, rho, &out[0], &out[1], &out[2]);
 }
 
 /* ---- building blocks exported for unit pins ----------------------------- */

@@ -32,6 +32,12 @@ Z_EPS = 1.0e-6
 
 SEEDS = {"random_4096x2048": 1905, "roofline_8192": 5727, "serving": 2019}
 
+# Liquid nitromethane, Cochran-Chan equation of state (Eqs. (2)-(4), Table 1):
+# (Gamma_0, A [Pa], B [Pa], C, D, rho_0 [kg/m3]); c_v = 1714 J/(kg K).
+NM_CC = (1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0)
+NM_CV = 1714.0
+RHO_NM = 1134.0           # Sec. 2.4
+
 
 @dataclass
 class Scenario:
@@ -52,6 +58,8 @@ class Scenario:
     zeps: float = Z_EPS
     steps: int = 0                        # step count of the workload
     t_end: float = 0.0                    # end time of the workload (0: none)
+    eos2: int = 0                         # liquid EoS: 0 stiffened gas, 1 Cochran-Chan
+    cc: tuple = NM_CC                     # Cochran-Chan parameters when eos2 == 1
     meta: dict = field(default_factory=dict)
 
 
@@ -74,6 +82,33 @@ def stiffened_gas_shock(p1: float, rho0: float = RHO_WATER, p0: float = P_AMBIEN
     c0 = math.sqrt(gamma * P0 / rho0)
     S = c0 * math.sqrt((gamma + 1.0) / (2.0 * gamma) * ratio + (gamma - 1.0) / (2.0 * gamma))
     u1 = S * (1.0 - rho0 / rho1)
+    return rho1, u1, S
+
+
+def _cc_energy(rho: float, p: float, cc=NM_CC) -> float:
+    """Specific internal energy of the Cochran-Chan liquid, Eq. (2) solved for e."""
+    G, A, B, C, D, r0 = cc
+    v = r0 / rho
+    pref = A * v ** (-C) - B * v ** (-D)
+    eref = (-A / (r0 * (1.0 - C)) * (v ** (1.0 - C) - 1.0)
+            + B / (r0 * (1.0 - D)) * (v ** (1.0 - D) - 1.0))
+    return eref + (p - pref) / (rho * G)
+
+
+def cochran_chan_shock(p1: float, rho0: float = RHO_NM, p0: float = P_AMBIENT, cc=NM_CC):
+    """State behind a right-running shock of pressure p1 into the Cochran-Chan
+    liquid at rest (the Hugoniot initialisation of the shocked region of
+    Sec. 2.4): the density solves the energy jump condition
+    e1 - e0 = (p1 + p0)(1/rho0 - 1/rho1)/2.  Returns (rho1, u1, shock_speed)."""
+    from scipy.optimize import brentq
+    e0 = _cc_energy(rho0, p0, cc)
+
+    def f(r1):
+        return _cc_energy(r1, p1, cc) - e0 - 0.5 * (p1 + p0) * (1.0 / rho0 - 1.0 / r1)
+
+    rho1 = brentq(f, rho0 * (1.0 + 1e-9), rho0 * 4.0, xtol=1e-12, rtol=1e-15, maxiter=500)
+    u1 = math.sqrt((p1 - p0) * (1.0 / rho0 - 1.0 / rho1))
+    S = u1 / (1.0 - rho0 / rho1)
     return rho1, u1, S
 
 
@@ -201,20 +236,17 @@ def shock_tube_1d(nx: int = 1000, ny: int = 1, x0: float = 0.7, length: float = 
 
 def single_bubble(nx: int = 1024, ny: int = 512, dx: float = 1.0e-5, radius: float = 64.0,
                   centre=(400.0, 256.0), shock_x: float = 320.0, p_shock: float = 1.0e9,
-                  steps: int = 2000, eps: float = Z_EPS) -> Scenario:
+                  steps: int = 2000, eps: float = Z_EPS, liquid: str = "water") -> Scenario:
     """One air bubble in water hit by a planar 1 GPa shock; the shocked water
     occupies x < shock_x (cell units).  Mirror symmetric about y = ny/2 when
     the centre lies on it."""
     prim = _blank(nx, ny)
-    rho1, u1, S = stiffened_gas_shock(p_shock)
-    ns = int(shock_x)
-    prim[2, :, :ns] = rho1
-    prim[3, :, :ns] = u1
-    prim[5, :, :ns] = p_shock
+    (rho1, u1, S), kw = _liquid(prim, liquid, p_shock, int(shock_x))
     _paint_bubble(prim[0], centre[0], centre[1], radius)
     return Scenario("single_bubble", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
                     steps=steps, meta=dict(p_shock=p_shock, shock_speed=S, rho1=rho1, u1=u1,
-                                           radius=radius, centre=centre, shock_x=shock_x))
+                                           radius=radius, centre=centre, shock_x=shock_x,
+                                           liquid=liquid), **kw)
 
 
 def random_bubbles(nx: int, ny: int, nbubbles: int, rmin: float, rmax: float, gap: float,
@@ -300,9 +332,25 @@ def _paint_bubble_periodic_y(w: np.ndarray, xc: float, yc: float, R: float) -> N
             _paint_bubble(w, xc, yc + shift, R)
 
 
+def _liquid(prim: np.ndarray, liquid: str, p_shock: float, strip: int):
+    """Fill the liquid density and the shocked strip; returns (post-shock state,
+    Scenario EoS keyword arguments)."""
+    if liquid == "nm":
+        prim[2] = RHO_NM
+        rho1, u1, S = cochran_chan_shock(p_shock)
+        kw = dict(eos2=1, cc=NM_CC)
+    else:
+        rho1, u1, S = stiffened_gas_shock(p_shock)
+        kw = {}
+    prim[2, :, :strip] = rho1
+    prim[3, :, :strip] = u1
+    prim[5, :, :strip] = p_shock
+    return (rho1, u1, S), kw
+
+
 def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip: int = 500,
                   p_shock: float = 1.0e9, dx: float = 1.0e-6, eps: float = Z_EPS,
-                  steps: int = 0) -> Scenario:
+                  steps: int = 0, liquid: str = "water") -> Scenario:
     """Square array of equal cavities (Sec. 2.4, Fig. 1(b)): spacing from
     Eq. (6_1), domain width = one spacing with periodic top/bottom walls, a
     shocked strip of `strip` cells at the transmissive left wall."""
@@ -310,10 +358,7 @@ def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip:
     ny = int(round(delta))
     nx = int(length)
     prim = _blank(nx, ny)
-    rho1, u1, S = stiffened_gas_shock(p_shock)
-    prim[2, :, :strip] = rho1
-    prim[3, :, :strip] = u1
-    prim[5, :, :strip] = p_shock
+    (rho1, u1, S), kw = _liquid(prim, liquid, p_shock, strip)
     R = 0.5 * d_c
     x = strip + 0.5 * delta
     centres = []
@@ -324,13 +369,14 @@ def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip:
     return Scenario("regular_array", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
                     bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
                     meta=dict(spacing=delta, ncavities=len(centres), p_shock=p_shock,
-                              shock_speed=S, bubbles=np.array(centres)))
+                              shock_speed=S, bubbles=np.array(centres), liquid=liquid), **kw)
 
 
 def random_cavities(d_c: int = 100, phi: float = 0.08, length: int = 24000, width: int = 2000,
                     strip: int = 500, min_spacing: float = 2.5, p_shock: float = 1.0e9,
                     dx: float = 1.0e-6, seed: int = 1905, eps: float = Z_EPS,
-                    steps: int = 0, max_draws: int = 2_000_000) -> Scenario:
+                    steps: int = 0, max_draws: int = 2_000_000,
+                    liquid: str = "water") -> Scenario:
     """Random field of equal cavities (Sec. 2.4, Fig. 1(c)): the count from
     Eq. (7) over the region ahead of the shocked strip, centres uniform with a
     minimum centre-to-centre distance of `min_spacing` diameters (Sec. 3),
@@ -358,17 +404,14 @@ def random_cavities(d_c: int = 100, phi: float = 0.08, length: int = 24000, widt
         xs[k], ys[k] = x, y
         k += 1
     prim = _blank(nx, ny)
-    rho1, u1, S = stiffened_gas_shock(p_shock)
-    prim[2, :, :strip] = rho1
-    prim[3, :, :strip] = u1
-    prim[5, :, :strip] = p_shock
+    (rho1, u1, S), kw = _liquid(prim, liquid, p_shock, strip)
     for x, y in zip(xs, ys):
         _paint_bubble_periodic_y(prim[0], x, y, R)
     cen = np.stack([xs, ys, np.full(ncav, R)], axis=1)
     return Scenario("random_cavities", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
                     bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
                     meta=dict(seed=seed, ncavities=ncav, porosity_target=phi, p_shock=p_shock,
-                              shock_speed=S, bubbles=cen, nbubbles=ncav))
+                              shock_speed=S, bubbles=cen, nbubbles=ncav, liquid=liquid), **kw)
 
 
 def uniform_state(nx: int, ny: int, dx: float = 1.0e-3, z1: float = Z_EPS,
