@@ -82,11 +82,22 @@ extern "C" {
 #define MF_P      9
 #define MF_C     10
 
-/* A stiffened-gas phase: p = (gamma - 1) rho e - gamma p_inf (Eq. (2) with
- * constant reference terms).  Air: p_inf = 0. */
+/* Equation of state of a phase, in the Mie-Grueneisen form of Eq. (2),
+ * p = p_ref(rho) + rho Gamma (e - e_ref(rho)):
+ *  MF_EOS_STIFFENED:    p = (gamma - 1) rho e - gamma p_inf (constant reference
+ *                       terms; air: the ideal gas, p_inf = 0);
+ *  MF_EOS_COCHRAN_CHAN: Gamma = gamma0, p_ref and e_ref of Eqs. (3)-(4) with
+ *                       the constants A, B (Pa), C, D and rho0 (Table 1).
+ *  Phase 1 (the gas) must be MF_EOS_STIFFENED. */
+#define MF_EOS_STIFFENED     0
+#define MF_EOS_COCHRAN_CHAN  1
+
 typedef struct {
+    int32_t kind;
+    int32_t reserved;
     double gamma;
     double p_inf;
+    double gamma0, A, B, C, D, rho0;
 } mf_material;
 
 /* Uniform Cartesian grid (Sec. 3), cell sizes in metres. */

@@ -34,10 +34,21 @@ bool valid_grid(const mf_grid *g) {
 
 bool valid_materials(const mf_material *mat) {
     if (!mat) return false;
-    for (int k = 0; k < 2; ++k)
-        if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
-            !isfinite(mat[k].p_inf))
+    for (int k = 0; k < 2; ++k) {
+        if (mat[k].kind == MF_EOS_STIFFENED) {
+            if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
+                !isfinite(mat[k].p_inf))
+                return false;
+        } else if (mat[k].kind == MF_EOS_COCHRAN_CHAN && k == 1) {
+            const mf_material &m = mat[k];
+            if (!(m.gamma0 > 0.0) || !(m.rho0 > 0.0) || !isfinite(m.gamma0) || !isfinite(m.A) ||
+                !isfinite(m.B) || !isfinite(m.C) || !isfinite(m.D) || !isfinite(m.rho0) ||
+                m.C == 1.0 || m.D == 1.0)
+                return false;
+        } else {
             return false;
+        }
+    }
     return true;
 }
 
@@ -90,9 +101,27 @@ void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_optio
     d.zlo = opt->z_floor;
     d.zhi = 1.0 - opt->z_floor;
     d.g1 = 1.0 / (mat[0].gamma - 1.0);
-    d.g2 = 1.0 / (mat[1].gamma - 1.0);
     d.h1 = (mat[0].gamma * mat[0].p_inf) * d.g1;
-    d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
+    d.eos2 = mat[1].kind;
+    if (mat[1].kind == MF_EOS_COCHRAN_CHAN) {
+        const mf_material &m = mat[1];
+        d.ciG = 1.0 / m.gamma0;
+        d.g2 = d.ciG;
+        d.h2 = 0.0;
+        d.cA = m.A;
+        d.cB = m.B;
+        d.cC = m.C;
+        d.cD = m.D;
+        d.crho0 = m.rho0;
+        d.ckA = -m.A / (m.rho0 * (1.0 - m.C));
+        d.ckB = m.B / (m.rho0 * (1.0 - m.D));
+        d.cAC = m.A * m.C;
+        d.cBD = m.B * m.D;
+    } else {
+        d.g2 = 1.0 / (mat[1].gamma - 1.0);
+        d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
+        d.ciG = d.cA = d.cB = d.cC = d.cD = d.crho0 = d.ckA = d.ckB = d.cAC = d.cBD = 0.0;
+    }
 }
 
 }  // namespace meso

@@ -47,12 +47,23 @@ namespace meso {
 // reciprocal and square root.
 template <class T, bool FAST> struct Ar;
 template <> struct Ar<double, false> {
+    // v^-C and v^-D of the Cochran-Chan reference curves
+    static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
+                                              double &vd) {
+        vc = pow(v, -C);
+        vd = pow(v, -D);
+    }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
     static __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
     static __device__ __forceinline__ double big() { return 1.0e300; }
 };
 template <> struct Ar<double, true> {
+    static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
+                                              double &vd) {
+        vc = pow(v, -C);
+        vd = pow(v, -D);
+    }
     static __device__ __forceinline__ double rcp(double a) {
         const double r = __builtin_amdgcn_rcp(a);
         const double e = __builtin_fma(-a, r, 1.0);
@@ -64,6 +75,11 @@ template <> struct Ar<double, true> {
     static __device__ __forceinline__ double big() { return 1.0e300; }
 };
 template <bool FAST> struct Ar<float, FAST> {
+    static __device__ __forceinline__ void pw(float v, float C, float D, float &vc, float &vd) {
+        const float l = __builtin_amdgcn_logf(v);        // log2 v
+        vc = __builtin_amdgcn_exp2f(-C * l);
+        vd = __builtin_amdgcn_exp2f(-D * l);
+    }
     static __device__ __forceinline__ float div(float a, float b) {
         return a * __builtin_amdgcn_rcpf(b);
     }
@@ -73,14 +89,43 @@ template <bool FAST> struct Ar<float, FAST> {
     static __device__ __forceinline__ float big() { return FLT_MAX; }
 };
 
+// Mixture constants: every phase in the Mie-Grueneisen form of Eq. (2),
+// rho_k e_k = phi_k(rho_k) + p / Gamma_k, so that rho e = p xi + eta with
+// xi = sum z_k / Gamma_k and eta = sum z_k phi_k.  g = 1/Gamma; h = phi of a
+// stiffened gas (constant); a Cochran-Chan liquid (eos2 = 1) has a density
+// dependent phi (Eqs. (3)-(4)).
 template <class T> struct Mix {
     T g1, g2, h1, h2;
+    int eos2;
+    T A, B, C, D, rho0, iG, kA, kB, AC, BD;
 };
 
 template <class T> __device__ __forceinline__ Mix<T> mix_of(const Desc &d) {
     Mix<T> m;
     m.g1 = (T)d.g1; m.g2 = (T)d.g2; m.h1 = (T)d.h1; m.h2 = (T)d.h2;
+    m.eos2 = d.eos2;
+    m.A = (T)d.cA; m.B = (T)d.cB; m.C = (T)d.cC; m.D = (T)d.cD; m.rho0 = (T)d.crho0;
+    m.iG = (T)d.ciG; m.kA = (T)d.ckA; m.kB = (T)d.ckB; m.AC = (T)d.cAC; m.BD = (T)d.cBD;
     return m;
+}
+
+// Cochran-Chan liquid at partial density a2 and volume fraction z2:
+// eta2 = z2 phi(rho2) and psi2 = z2 rho2 phi'(rho2), the term the density
+// dependence of phi adds to the frozen sound speed
+// rho c^2 = (p (1 + xi) + eta - psi) / xi.
+template <class T, bool FAST>
+__device__ __forceinline__ void liquid_terms(const Mix<T> &m, T a2, T z2, T &eta2, T &psi2) {
+    const T rho2 = Ar<T, FAST>::div(a2, z2);
+    const T v = Ar<T, FAST>::div(m.rho0, rho2);
+    T vc, vd;
+    Ar<T, FAST>::pw(v, m.C, m.D, vc, vd);
+    const T pref = m.A * vc - m.B * vd;
+    const T eref = m.kA * (v * vc - T(1)) + m.kB * (v * vd - T(1));
+    const T rdpref = m.AC * vc - m.BD * vd;
+    const T phi = rho2 * eref - pref * m.iG;
+    const T rphi = (rho2 * eref + pref) - rdpref * m.iG;
+    eta2 = z2 * phi;
+    psi2 = z2 * rphi;
 }
 
 // Ghost-cell index map: transmissive copies the edge cell, periodic wraps.
@@ -100,7 +145,14 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[
     const S z = q[5];
     const S z2 = S(1) - z;
     const S xi = z * m.g1 + z2 * m.g2;
-    const S eta = z * m.h1 + z2 * m.h2;
+    S eta, psi = S(0);
+    if (m.eos2 == 1) {
+        S eta2;
+        liquid_terms<S, FAST>(m, q[1], z2, eta2, psi);
+        eta = z * m.h1 + eta2;
+    } else {
+        eta = z * m.h1 + z2 * m.h2;
+    }
     S ixi;
     if constexpr (FAST) {   // one reciprocal for both 1/rho and 1/xi
         const S inv = Ar<S, FAST>::rcp(rho * xi);
@@ -115,7 +167,8 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[
     const S ke = S(0.5) * (q[2] * un + q[3] * ut);
     const S rhoe = q[4] - ke;
     const S p = (rhoe - eta) * ixi;
-    rc2 = (p * (S(1) + xi) + eta) * ixi;
+    if (m.eos2 == 1) rc2 = ((p * (S(1) + xi) + eta) - psi) * ixi;
+    else rc2 = (p * (S(1) + xi) + eta) * ixi;
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
 }
 
@@ -164,8 +217,16 @@ __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R>
     const R un = w[2], ut = w[3], p = w[4], z = w[5];
     const R z2 = R(1) - z;
     const R xi = z * m.g1 + z2 * m.g2;
-    const R eta = z * m.h1 + z2 * m.h2;
-    const R num = p * (R(1) + xi) + eta;
+    R eta, num;
+    if (m.eos2 == 1) {
+        R eta2, psi2;
+        liquid_terms<R, FAST>(m, w[1], z2, eta2, psi2);
+        eta = z * m.h1 + eta2;
+        num = (p * (R(1) + xi) + eta) - psi2;
+    } else {
+        eta = z * m.h1 + z2 * m.h2;
+        num = p * (R(1) + xi) + eta;
+    }
     if constexpr (FAST) c = num * Ar<R, FAST>::rsq(num * (xi * rho));   // sqrt(num / (xi rho))
     else c = Ar<R, FAST>::sqrt_(Ar<R, FAST>::div(num, xi * rho));
     const R E = (p * xi + eta) + R(0.5) * (rho * (un * un + ut * ut));

@@ -50,7 +50,12 @@ struct Desc {
     double dx, dy, cfl;      // cell sizes and CFL number (used by the batched dt kernel)
     double idx, idy;         // 1/dx, 1/dy
     double zlo, zhi;         // eps, 1 - eps of the pointwise stage
-    double g1, g2, h1, h2;   // mixture constants 1/(gamma-1), gamma pinf/(gamma-1)
+    double g1, g2, h1, h2;   // mixture constants 1/Gamma_k, phi_k of stiffened gases
+    int eos2;                // liquid EoS: 0 stiffened gas, 1 Cochran-Chan
+    int pad_;
+    // Cochran-Chan liquid: A, B, C, D, rho0, 1/Gamma0, -A/(rho0(1-C)), B/(rho0(1-D)),
+    // A*C, B*D
+    double cA, cB, cC, cD, crho0, ciG, ckA, ckB, cAC, cBD;
 };
 
 // Host helpers shared by the solver and the server (meso_api.hip).

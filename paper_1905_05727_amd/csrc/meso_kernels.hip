@@ -101,6 +101,7 @@ template <class S>
 __global__ void prim_to_cons_kernel(Desc d, int dst_idx, const double *prim) {
     const long long N = (long long)d.nx * d.ny;
     S *dst = (S *)d.buf[dst_idx];
+    const Mix<double> m = mix_of<double>(d);
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
          k += (long long)gridDim.x * blockDim.x) {
         const double z = prim[k], r1 = prim[N + k], r2 = prim[2 * N + k];
@@ -109,7 +110,14 @@ __global__ void prim_to_cons_kernel(Desc d, int dst_idx, const double *prim) {
         const double a1 = z * r1, a2 = z2 * r2;
         const double rho = a1 + a2;
         const double xi = z * d.g1 + z2 * d.g2;
-        const double eta = z * d.h1 + z2 * d.h2;
+        double eta;
+        if (d.eos2 == 1) {
+            double eta2, psi2;
+            liquid_terms<double, false>(m, a2, z2, eta2, psi2);
+            eta = z * d.h1 + eta2;
+        } else {
+            eta = z * d.h1 + z2 * d.h2;
+        }
         const double E = (p * xi + eta) + 0.5 * (rho * (u * u + v * v));
         const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
         const long long o = (long long)j * d.pitch + i;

@@ -48,7 +48,30 @@ class Grid(C.Structure):
 
 
 class Material(C.Structure):
-    _fields_ = [("gamma", C.c_double), ("p_inf", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("gamma", C.c_double),
+                ("p_inf", C.c_double), ("gamma0", C.c_double), ("A", C.c_double),
+                ("B", C.c_double), ("C", C.c_double), ("D", C.c_double), ("rho0", C.c_double)]
+
+
+EOS_STIFFENED, EOS_COCHRAN_CHAN = 0, 1
+
+
+def stiffened(gamma: float, p_inf: float = 0.0) -> Material:
+    """Stiffened gas p = (gamma - 1) rho e - gamma p_inf (air: p_inf = 0)."""
+    return Material(EOS_STIFFENED, 0, float(gamma), float(p_inf), 0, 0, 0, 0, 0, 0)
+
+
+def cochran_chan(gamma0, A, B, C_, D, rho0) -> Material:
+    """Cochran-Chan liquid (Eqs. (2)-(4)); constants as in Table 1."""
+    return Material(EOS_COCHRAN_CHAN, 0, 0.0, 0.0, float(gamma0), float(A), float(B),
+                    float(C_), float(D), float(rho0))
+
+
+def materials_of(sc) -> "C.Array":
+    """(gas, liquid) materials of a scenario."""
+    liquid = cochran_chan(*sc.cc) if getattr(sc, "eos2", 0) == 1 else stiffened(sc.gamma2,
+                                                                                sc.pinf2)
+    return (Material * 2)(stiffened(sc.gamma1, sc.pinf1), liquid)
 
 
 class ServerConfig(C.Structure):
@@ -150,7 +173,7 @@ class Solver:
 
     def __init__(self, nx, ny, dx, dy, *, gamma1=1.4, pinf1=0.0, gamma2=4.4, pinf2=6.0e8,
                  cfl=0.4, z_floor=1e-6, limiter="vanleer", precision="fp64", fused=True,
-                 bc=("transmissive",) * 4, workspace="torch", stream=None):
+                 bc=("transmissive",) * 4, workspace="torch", stream=None, liquid=None):
         import torch
         lib = load_library()
         if not torch.cuda.is_available():
@@ -159,7 +182,8 @@ class Solver:
         self.precision = precision
         self._lib = lib
         self._grid = make_grid(nx, ny, dx, dy, bc)
-        mats = (Material * 2)(Material(gamma1, pinf1), Material(gamma2, pinf2))
+        mats = (Material * 2)(stiffened(gamma1, pinf1),
+                              liquid if liquid is not None else stiffened(gamma2, pinf2))
         opt = Options(float(cfl), float(z_floor), LIMITER[limiter], PRECISION[precision],
                       1 if fused else 0, 0)
         nbytes = int(lib.mf_workspace_bytes(C.byref(self._grid), PRECISION[precision]))
@@ -183,7 +207,7 @@ class Solver:
     def from_scenario(cls, sc, precision="fp64", fused=True, **kw):
         s = cls(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1, gamma2=sc.gamma2,
                 pinf2=sc.pinf2, cfl=sc.cfl, z_floor=sc.zeps, limiter=sc.limiter,
-                precision=precision, fused=fused, bc=sc.bc, **kw)
+                precision=precision, fused=fused, bc=sc.bc, liquid=materials_of(sc)[1], **kw)
         s.set_primitive(sc.prim)
         return s
 

@@ -44,8 +44,7 @@ class Server:
 
     def submit(self, sc, nsteps: int) -> int:
         g = meso.make_grid(sc.nx, sc.ny, sc.dx, sc.dy, sc.bc)
-        mats = (meso.Material * 2)(meso.Material(sc.gamma1, sc.pinf1),
-                                   meso.Material(sc.gamma2, sc.pinf2))
+        mats = meso.materials_of(sc)
         opt = meso.Options(sc.cfl, sc.zeps, meso.LIMITER[self.limiter],
                            meso.PRECISION[self.precision], 1, 0)
         prim = np.ascontiguousarray(sc.prim, dtype=np.float64)

@@ -50,7 +50,7 @@ def test_workspace_bytes():
 def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
     lib = meso.load_library()
     grid = grid or meso.make_grid(16, 8, 1e-3, 1e-3)
-    mats = mats or (meso.Material * 2)(meso.Material(1.4, 0.0), meso.Material(4.4, 6e8))
+    mats = mats or (meso.Material * 2)(meso.stiffened(1.4, 0.0), meso.stiffened(4.4, 6e8))
     opt = opt or meso.Options(0.4, 1e-6, 0, 0, 1, 0)
     h = C.c_void_p()
     st = lib.mf_create(C.byref(grid), mats, C.byref(opt), ws, ws_bytes, None, C.byref(h))
@@ -63,8 +63,14 @@ def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
     dict(grid=meso.make_grid(16, 8, 1e-3, 1e-3, ("periodic", "transmissive", "transmissive",
                                                   "transmissive"))),
     dict(grid=meso.make_grid(16, 8, 1e-3, 1e-3, (3, 0, 0, 0))),
-    dict(mats=(meso.Material * 2)(meso.Material(1.0, 0.0), meso.Material(4.4, 6e8))),
-    dict(mats=(meso.Material * 2)(meso.Material(1.4, -1.0), meso.Material(4.4, 6e8))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.0, 0.0), meso.stiffened(4.4, 6e8))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, -1.0), meso.stiffened(4.4, 6e8))),
+    dict(mats=(meso.Material * 2)(meso.cochran_chan(1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0),
+                                  meso.stiffened(4.4, 6e8))),          # the gas must be a gas
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0),
+                                  meso.cochran_chan(1.19, 0.819e9, 1.51e9, 1.0, 1.42, 1134.0))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0),
+                                  meso.cochran_chan(1.19, 0.819e9, 1.51e9, 4.53, 1.42, -1.0))),
     dict(opt=meso.Options(0.0, 1e-6, 0, 0, 1, 0)),
     dict(opt=meso.Options(1.5, 1e-6, 0, 0, 1, 0)),
     dict(opt=meso.Options(0.4, 0.6, 0, 0, 1, 0)),

@@ -1,0 +1,123 @@
+"""GPU path with the Cochran-Chan nitromethane liquid (Eqs. (2)-(4), Table 1)
+against the FP64 oracle.
+
+The device's FP64 pow and the host's may differ in the last bit, so the FP64
+gate here is a stated tolerance: every conserved value within 1e-10 relative
+(of its plane's magnitude scale) after the run, plus relative L1 <= 1e-12 per
+plane.  FP32 modes: the density / pressure L1 gates of the water workloads."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_05727_amd import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1905_05727_amd import meso  # noqa: E402
+
+BCO = {"transmissive": 0, "periodic": 1}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_of(sc):
+    bc = [BCO[b] for b in sc.bc]
+    P = oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl, zeps=sc.zeps, eos2=sc.eos2,
+                       cc=sc.cc, bc_xlo=bc[0], bc_xhi=bc[1], bc_ylo=bc[2], bc_yhi=bc[3])
+    o = oracle.Oracle(P)
+    o.set_primitive(sc.prim)
+    return o
+
+
+def close_fp64(U, V, what):
+    scale = np.abs(V).reshape(V.shape[0], -1).max(axis=1)
+    scale[3] = scale[2] = max(scale[2], scale[3])
+    d = np.abs(U - V).reshape(V.shape[0], -1).max(axis=1)
+    l1 = np.abs(U - V).reshape(V.shape[0], -1).sum(axis=1) / \
+        np.maximum(np.abs(V).reshape(V.shape[0], -1).sum(axis=1), 1e-300)
+    exact = float(np.mean(U == V))
+    say(f"{what}: max rel diff per plane {d / scale}, L1 {l1}, exactly equal {exact:.4f}")
+    assert np.all(d <= 1e-10 * scale) and np.all(l1[[0, 1, 2, 4, 5]] <= 1e-12)
+
+
+def nm_bubble(nx=240, ny=120, periodic=False):
+    sc = S.single_bubble(nx=nx, ny=ny, dx=1e-6, radius=ny / 5, centre=(nx * 0.55, ny / 2),
+                         shock_x=nx * 0.3, liquid="nm", p_shock=7.81e9)
+    if periodic:
+        sc.bc = ("periodic",) * 4
+    return sc
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_nm_bubble_fp64_matches_oracle(fused):
+    sc = nm_bubble()
+    say(f"case: NM bubble {sc.nx}x{sc.ny}, 7.81 GPa, fused={fused}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64", fused=fused) as s:
+        s.run_steps(25)
+        U = s.read_conserved()
+        t, n, _ = s.time()
+    o.run(25)
+    assert n == 25 and abs(t - o.t) <= 1e-12 * o.t
+    close_fp64(U, o.U, "NM bubble")
+
+
+@pytest.mark.parametrize("prec", ["fp32_fp64acc", "fp32"])
+def test_nm_reduced_precision(prec):
+    sc = nm_bubble(200, 100)
+    say(f"case: NM bubble 200x100, 300 steps, {prec}")
+    o = oracle_of(sc)
+    o.run(300)
+    ref = o.primitive()
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(300)
+        rho, p = s.read_field("rho"), s.read_field("p")
+    e_rho = float(np.abs(rho - ref["rho"]).sum() / np.abs(ref["rho"]).sum())
+    e_p = float(np.abs(p - ref["p"]).sum() / np.abs(ref["p"]).sum())
+    say(f"{prec}: rel L1 rho {e_rho:.3e} p {e_p:.3e}")
+    assert e_rho <= 1e-4 and e_p <= 1e-3
+
+
+def test_nm_regular_array_paper_grid_sampled():
+    """The paper's regular-array grid (24000 x 313, 100 cells per cavity,
+    periodic top/bottom) in nitromethane at 7.81 GPa: one step after 3 is
+    checked on sampled cells."""
+    sc = S.regular_array(liquid="nm", p_shock=7.81e9)
+    say(f"case: NM regular array {sc.nx}x{sc.ny}")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(3)
+        U0 = s.read_conserved()
+        t0, n0, _ = s.time()
+        s.run_steps(1)
+        U1 = s.read_conserved()
+        _, _, dt = s.time()
+    o = oracle_of(sc)
+    o.U[...] = U0
+    o.t, o.step = t0, n0
+    dto, _ = o.cfl_dt()
+    assert abs(dt - dto) <= 1e-13 * dto
+    rng = np.random.default_rng(2)
+    cells = rng.integers(0, sc.nx * sc.ny, 4000)
+    cells = np.concatenate([cells, np.arange(0, sc.nx * sc.ny, sc.nx)[:50],
+                            np.arange(490, 510) + 156 * sc.nx])
+    exp = o.step_cells(U0, n0, dt, cells)      # same dt: compares the update itself
+    close_fp64(U1.reshape(6, -1)[:, cells], exp, "NM regular array sampled")
+
+
+def test_nm_conservation_on_gpu():
+    sc = nm_bubble(160, 80, periodic=True)
+    say("case: NM periodic conservation")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        U0 = s.read_conserved()
+        s.run_steps(120)
+        U1 = s.read_conserved()
+    s0, s1 = U0[:5].sum(axis=(1, 2)), U1[:5].sum(axis=(1, 2))
+    scale = np.abs(U0[:5]).sum(axis=(1, 2))
+    scale[2] = scale[3] = np.abs(U0[2]).sum() + np.abs(U0[3]).sum()
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * 120 * scale)
