@@ -50,7 +50,9 @@ class _Problem(C.Structure):
                 ("gamma2", C.c_double), ("pinf2", C.c_double), ("cfl", C.c_double),
                 ("zeps", C.c_double), ("limiter", C.c_int32), ("eos2", C.c_int32),
                 ("cc_gamma0", C.c_double), ("cc_A", C.c_double), ("cc_B", C.c_double),
-                ("cc_C", C.c_double), ("cc_D", C.c_double), ("cc_rho0", C.c_double)]
+                ("cc_C", C.c_double), ("cc_D", C.c_double), ("cc_rho0", C.c_double),
+                ("reactive", C.c_int32), ("pad2_", C.c_int32), ("rx_C", C.c_double),
+                ("rx_Ta", C.c_double), ("rx_Q", C.c_double), ("rx_cv2", C.c_double)]
 
 
 _lib = None
@@ -124,11 +126,20 @@ class Problem:
     # liquid equation of state: 0 stiffened gas (gamma2, pinf2), 1 Cochran-Chan
     eos2: int = 0
     cc: tuple = (1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0)   # Gamma0, A, B, C, D, rho0
+    # reactive liquid (7th plane z2 rho2 lambda): Arrhenius C [1/s], Ta [K], Q [J/kg]
+    # (Table 3) and c_v,2 [J/(kg K)] (Table 1); requires eos2 == 1
+    reactive: int = 0
+    rx: tuple = (2.6e9, 11350.0, 4.46e6, 1714.0)
+
+    @property
+    def nplanes(self) -> int:
+        return 7 if self.reactive else 6
 
     def _c(self) -> _Problem:
         return _Problem(self.nx, self.ny, self.dx, self.dy, self.bc_xlo, self.bc_xhi,
                         self.bc_ylo, self.bc_yhi, self.gamma1, self.pinf1, self.gamma2,
-                        self.pinf2, self.cfl, self.zeps, self.limiter, self.eos2, *self.cc)
+                        self.pinf2, self.cfl, self.zeps, self.limiter, self.eos2, *self.cc,
+                        self.reactive, 0, *self.rx)
 
 
 class Oracle:
@@ -137,14 +148,14 @@ class Oracle:
     def __init__(self, prob: Problem):
         self.prob = prob
         self._p = prob._c()
-        self.U = np.zeros((6, prob.ny, prob.nx), dtype=np.float64)
+        self.U = np.zeros((prob.nplanes, prob.ny, prob.nx), dtype=np.float64)
         self.t = 0.0
         self.step = 0
         self.last_dt = 0.0
 
     # -- state -------------------------------------------------------------
     def set_primitive(self, prim: np.ndarray) -> None:
-        """prim: (6, ny, nx) planes z1, rho1, rho2, u, v, p."""
+        """prim: (6, ny, nx) planes z1, rho1, rho2, u, v, p (+ lambda when reactive)."""
         prim = np.ascontiguousarray(prim, dtype=np.float64)
         assert prim.shape == self.U.shape
         _load().or_prim_to_cons(C.byref(self._p), _dp(prim), _dp(self.U))
@@ -153,9 +164,12 @@ class Oracle:
         self.U[...] = U
 
     def primitive(self) -> dict:
-        out = np.empty((6, self.prob.ny, self.prob.nx), dtype=np.float64)
+        out = np.empty((self.prob.nplanes, self.prob.ny, self.prob.nx), dtype=np.float64)
         _load().or_cons_to_prim(C.byref(self._p), _dp(self.U), _dp(out))
-        return dict(rho=out[0], u=out[1], v=out[2], p=out[3], c=out[4], z1=out[5])
+        d = dict(rho=out[0], u=out[1], v=out[2], p=out[3], c=out[4], z1=out[5])
+        if self.prob.reactive:
+            d["lam"] = out[6]
+        return d
 
     # -- time stepping -----------------------------------------------------
     def max_speed(self) -> float:
@@ -198,9 +212,9 @@ class Oracle:
         return p, r, u
 
     def integrals(self) -> np.ndarray:
-        out = np.empty(6)
+        out = np.empty(7)
         _load().or_integrals(C.byref(self._p), _dp(self.U), _dp(out))
-        return out
+        return out[:self.prob.nplanes]
 
     def log_histogram(self, field: int, lo: float, dn: float, nbins: int, m_ref: float):
         f = np.empty(nbins)
@@ -212,7 +226,7 @@ class Oracle:
         """Post-step state at flat cell indices j*nx+i, from pre-step state U."""
         U = np.ascontiguousarray(U, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int64)
-        out = np.empty((6, cells.size), dtype=np.float64)
+        out = np.empty((self.prob.nplanes, cells.size), dtype=np.float64)
         _load().or_step_cells(C.byref(self._p), _dp(U), step, dt,
                               cells.ctypes.data_as(C.POINTER(C.c_int64)), cells.size, _dp(out))
         return out
@@ -244,9 +258,9 @@ def unit_face_states(wm, w0, wp, r, rc2, hl, limiter):
 def unit_hllc(prob: Problem, wL, wR) -> np.ndarray:
     wL = np.ascontiguousarray(wL, dtype=np.float64)
     wR = np.ascontiguousarray(wR, dtype=np.float64)
-    out = np.empty(7)
+    out = np.empty(8)
     _load().or_unit_hllc(C.byref(prob._c()), _dp(wL), _dp(wR), _dp(out))
-    return out
+    return out[:7]
 
 
 def unit_sweep_line(prob: Problem, q: np.ndarray, lam: float) -> np.ndarray:

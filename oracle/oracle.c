@@ -35,7 +35,7 @@
 #include <omp.h>
 #endif
 
-#define NV 6
+#define NV 7   /* largest number of components (with the reaction progress) */
 
 /* Problem description passed from Python (ctypes mirrors this layout). */
 typedef struct {
@@ -47,6 +47,9 @@ typedef struct {
     int32_t limiter;                        /* 0 van Leer, 1 minmod */
     int32_t eos2;                           /* liquid: 0 stiffened gas, 1 Cochran-Chan */
     double cc_gamma0, cc_A, cc_B, cc_C, cc_D, cc_rho0;   /* Eqs. (2)-(4), Table 1 */
+    int32_t reactive;                       /* 1: 7th plane z2 rho2 lambda + Arrhenius */
+    int32_t pad2_;
+    double rx_C, rx_Ta, rx_Q, rx_cv2;       /* Eq. (6), Table 3; c_v,2 of Table 1 */
 } or_problem;
 
 /* Mixture constants.  Every phase is written in the Mie-Grueneisen form of
@@ -60,6 +63,7 @@ typedef struct {
     double g1, g2, h1, h2;
     int eos2;
     double A, B, C, D, rho0, iG, kA, kB;
+    int nc;                                 /* components: 6, or 7 with z2 rho2 lambda */
 } mixc;
 
 static mixc mix_constants(const or_problem *P)
@@ -68,6 +72,7 @@ static mixc mix_constants(const or_problem *P)
     m.g1 = 1.0 / (P->gamma1 - 1.0);
     m.h1 = (P->gamma1 * P->pinf1) * m.g1;
     m.eos2 = P->eos2;
+    m.nc = P->reactive ? 7 : 6;
     if (P->eos2 == 1) {
         m.iG = 1.0 / P->cc_gamma0;
         m.g2 = m.iG;
@@ -144,6 +149,7 @@ static void cons_to_prim(const mixc *m, const double q[NV], double w[NV],
         rc2 = (p * (1.0 + xi) + eta) * ixi;
     }
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
+    if (m->nc == 7) w[6] = q[6] / q[1];     /* lambda: mass fraction of unreacted liquid */
     *r_out = r;
     *rc2_out = rc2;
 }
@@ -172,12 +178,12 @@ static double limit_slope(double a, double b, int limiter)
  *   d p/dt   + un d p/dx + rho c^2 d un/dx = 0
  *   d z/dt   + un d z/dx = 0                                                */
 static void face_states(const double wm[NV], const double w0[NV], const double wp[NV],
-                        double r, double rc2, double hl, int limiter,
+                        double r, double rc2, double hl, int limiter, int nc,
                         double wl[NV], double wh[NV])
 {
     double d[NV], s[NV];
     int c;
-    for (c = 0; c < NV; ++c)
+    for (c = 0; c < nc; ++c)
         d[c] = limit_slope(w0[c] - wm[c], wp[c] - w0[c], limiter);
     {
         double un = w0[2];
@@ -187,8 +193,9 @@ static void face_states(const double wm[NV], const double w0[NV], const double w
         s[3] = hl * (un * d[3]);
         s[4] = hl * (un * d[4] + rc2 * d[2]);
         s[5] = hl * (un * d[5]);
+        if (nc == 7) s[6] = hl * (un * d[6]);   /* lambda is advected */
     }
-    for (c = 0; c < NV; ++c) {
+    for (c = 0; c < nc; ++c) {
         wl[c] = (w0[c] - 0.5 * d[c]) - s[c];
         wh[c] = (w0[c] + 0.5 * d[c]) - s[c];
     }
@@ -197,8 +204,8 @@ static void face_states(const double wm[NV], const double w0[NV], const double w
 /* Per-side quantities of a face state for the HLLC solver. */
 typedef struct {
     double rho, un, ut, p, z, c, E;
-    double U[5];   /* a1, a2, rho un, rho ut, E   */
-    double F[5];   /* physical flux along the sweep */
+    double U[6];   /* a1, a2, rho un, rho ut, E (, a2 lambda) */
+    double F[6];   /* physical flux along the sweep           */
 } side_t;
 
 static void side_eval(const mixc *m, const double w[NV], side_t *s)
@@ -226,16 +233,20 @@ static void side_eval(const mixc *m, const double w[NV], side_t *s)
     s->F[2] = mn * un + p;
     s->F[3] = mn * ut;
     s->F[4] = (E + p) * un;
+    if (m->nc == 7) {
+        s->U[5] = w[1] * w[6];
+        s->F[5] = s->U[5] * un;
+    }
 }
 
 /* HLLC star-region flux of side K (K = L with S = S_L, or R with S = S_R),
  * together with the HLLC-consistent interface velocity used by the
  * non-conservative z1 term.                                                 */
-static void star_flux(const side_t *k, double S, double Ss, double out[7])
+static void star_flux(const side_t *k, double S, double Ss, int nc, double out[8])
 {
     double d = S - k->un;
     double chi = d / (S - Ss);
-    double us[5];
+    double us[6];
     int c;
     us[0] = chi * k->U[0];
     us[1] = chi * k->U[1];
@@ -245,11 +256,15 @@ static void star_flux(const side_t *k, double S, double Ss, double out[7])
     for (c = 0; c < 5; ++c) out[c] = k->F[c] + S * (us[c] - k->U[c]);
     out[5] = k->un + S * (chi - 1.0);   /* interface velocity u_f */
     out[6] = k->z;                      /* upwind face value of z1 */
+    if (nc == 7) {
+        us[5] = chi * k->U[5];
+        out[7] = k->F[5] + S * (us[5] - k->U[5]);
+    }
 }
 
 /* HLLC approximate Riemann solver (Sec. 3) with Davis wave-speed bounds.
  * out = (5 flux components, u_f, z_f).                                      */
-static void hllc(const mixc *m, const double wL[NV], const double wR[NV], double out[7])
+static void hllc(const mixc *m, const double wL[NV], const double wR[NV], double out[8])
 {
     side_t L, R;
     double SL, SR, dL, dR, Ss;
@@ -264,31 +279,35 @@ static void hllc(const mixc *m, const double wL[NV], const double wR[NV], double
     if (SL >= 0.0) {
         for (c = 0; c < 5; ++c) out[c] = L.F[c];
         out[5] = L.un; out[6] = L.z;
+        if (m->nc == 7) out[7] = L.F[5];
     } else if (SR <= 0.0) {
         for (c = 0; c < 5; ++c) out[c] = R.F[c];
         out[5] = R.un; out[6] = R.z;
+        if (m->nc == 7) out[7] = R.F[5];
     } else if (Ss > 0.0) {
-        star_flux(&L, SL, Ss, out);
+        star_flux(&L, SL, Ss, m->nc, out);
     } else if (Ss < 0.0) {
-        star_flux(&R, SR, Ss, out);
+        star_flux(&R, SR, Ss, m->nc, out);
     } else {
-        double a[7], b[7];
-        star_flux(&L, SL, Ss, a);
-        star_flux(&R, SR, Ss, b);
-        for (c = 0; c < 7; ++c) out[c] = 0.5 * (a[c] + b[c]);
+        double a[8], b[8];
+        int no = m->nc == 7 ? 8 : 7;
+        star_flux(&L, SL, Ss, m->nc, a);
+        star_flux(&R, SR, Ss, m->nc, b);
+        for (c = 0; c < no; ++c) out[c] = 0.5 * (a[c] + b[c]);
     }
 }
 
 /* Conservative update of the first five components and the non-conservative
  * z1 update  z -= lam * [ (z_f - z)_{+} u_{f,+} - (z_f - z)_{-} u_{f,-} ],
  * i.e. the discrete form of  dz/dt + d(uz)/dx - z du/dx = 0.               */
-static void update_cell(const double q[NV], const double flo[7], const double fhi[7],
-                        double lam, double qo[NV])
+static void update_cell(const double q[NV], const double flo[8], const double fhi[8],
+                        double lam, int nc, double qo[NV])
 {
     int c;
     double z = q[5];
     for (c = 0; c < 5; ++c) qo[c] = q[c] - lam * (fhi[c] - flo[c]);
     qo[5] = z - lam * ((fhi[6] - z) * fhi[5] - (flo[6] - z) * flo[5]);
+    if (nc == 7) qo[6] = q[6] - lam * (fhi[7] - flo[7]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -321,34 +340,35 @@ static void sweep_line(const mixc *m, long n, double *const qin[NV], double *con
     double *rc = rr + nw;             /* nw                               */
     double *WL = rc + nw;             /* nw * NV (low-face state)          */
     double *WH = WL + nw * NV;        /* nw * NV (high-face state)         */
-    double *FF = WH + nw * NV;        /* (n + 1) * 7, face f between f-1, f */
+    double *FF = WH + nw * NV;        /* (n + 1) * 8, face f between f-1, f */
+    int nc = m->nc;
 
     for (i = -2; i < n + 2; ++i) {
         double q[NV];
         long src = map_index(i, n, bc_lo, bc_hi);
-        for (c = 0; c < NV; ++c) q[c] = qin[c][src];
+        for (c = 0; c < nc; ++c) q[c] = qin[c][src];
         cons_to_prim(m, q, &W[(i + 2) * NV], &rr[i + 2], &rc[i + 2]);
     }
     for (i = -1; i < n + 1; ++i) {
         k = i + 2;
         face_states(&W[(k - 1) * NV], &W[k * NV], &W[(k + 1) * NV], rr[k], rc[k], hl,
-                    limiter, &WL[k * NV], &WH[k * NV]);
+                    limiter, nc, &WL[k * NV], &WH[k * NV]);
     }
     for (i = 0; i <= n; ++i) {
         /* face between cell i-1 (its high face) and cell i (its low face) */
-        hllc(m, &WH[(i + 1) * NV], &WL[(i + 2) * NV], &FF[i * 7]);
+        hllc(m, &WH[(i + 1) * NV], &WL[(i + 2) * NV], &FF[i * 8]);
     }
     for (i = 0; i < n; ++i) {
         double q[NV], qo[NV];
-        for (c = 0; c < NV; ++c) q[c] = qin[c][i];
-        update_cell(q, &FF[i * 7], &FF[(i + 1) * 7], lam, qo);
-        for (c = 0; c < NV; ++c) qout[c][i] = qo[c];
+        for (c = 0; c < nc; ++c) q[c] = qin[c][i];
+        update_cell(q, &FF[i * 8], &FF[(i + 1) * 8], lam, nc, qo);
+        for (c = 0; c < nc; ++c) qout[c][i] = qo[c];
     }
 }
 
 static size_t line_work_doubles(long n)
 {
-    return (size_t)(n + 4) * (2 * NV + 2) + (size_t)(n + 4) * NV + (size_t)(n + 1) * 7;
+    return (size_t)(n + 4) * (2 * NV + 2) + (size_t)(n + 4) * NV + (size_t)(n + 1) * 8;
 }
 
 /* X sweep of the whole grid: rows are lines, normal momentum = rho u.      */
@@ -367,13 +387,13 @@ static void sweep_x(const or_problem *P, const mixc *m, const double *U, double 
             int c;
             long i;
             /* line frame: (a1, a2, rho u, rho v, E, z) -- same order as U */
-            for (c = 0; c < NV; ++c) {
+            for (c = 0; c < m->nc; ++c) {
                 qi[c] = lin + c * nx;
                 qo[c] = lout + c * nx;
                 for (i = 0; i < nx; ++i) qi[c][i] = U[c * N + j * nx + i];
             }
             sweep_line(m, nx, qi, qo, P->bc_xlo, P->bc_xhi, lam, P->limiter, work);
-            for (c = 0; c < NV; ++c)
+            for (c = 0; c < m->nc; ++c)
                 for (i = 0; i < nx; ++i) V[c * N + j * nx + i] = qo[c][i];
         }
         free(work); free(lin); free(lout);
@@ -381,7 +401,7 @@ static void sweep_x(const or_problem *P, const mixc *m, const double *U, double 
 }
 
 /* Y sweep: columns are lines, normal momentum = rho v, tangential = rho u.  */
-static const int ymap[NV] = {0, 1, 3, 2, 4, 5};
+static const int ymap[NV] = {0, 1, 3, 2, 4, 5, 6};
 
 static void sweep_y(const or_problem *P, const mixc *m, const double *U, double *V, double lam)
 {
@@ -397,13 +417,13 @@ static void sweep_y(const or_problem *P, const mixc *m, const double *U, double 
             double *qi[NV], *qo[NV];
             int c;
             long j;
-            for (c = 0; c < NV; ++c) {
+            for (c = 0; c < m->nc; ++c) {
                 qi[c] = lin + c * ny;
                 qo[c] = lout + c * ny;
                 for (j = 0; j < ny; ++j) qi[c][j] = U[ymap[c] * N + j * nx + i];
             }
             sweep_line(m, ny, qi, qo, P->bc_ylo, P->bc_yhi, lam, P->limiter, work);
-            for (c = 0; c < NV; ++c)
+            for (c = 0; c < m->nc; ++c)
                 for (j = 0; j < ny; ++j) V[ymap[c] * N + j * nx + i] = qo[c][j];
         }
         free(work); free(lin); free(lout);
@@ -449,6 +469,7 @@ void or_prim_to_cons(const or_problem *P, const double *prim, double *U)
         U[3 * N + k] = rho * v;
         U[4 * N + k] = (p * xi + eta) + 0.5 * (rho * (u * u + v * v));
         U[5 * N + k] = z;
+        if (m.nc == 7) U[6 * N + k] = a2 * prim[6 * N + k];
     }
 }
 
@@ -460,8 +481,9 @@ void or_cons_to_prim(const or_problem *P, const double *U, double *out)
     for (k = 0; k < N; ++k) {
         double q[NV], w[NV], r, rc2;
         int c;
-        for (c = 0; c < NV; ++c) q[c] = U[c * N + k];
+        for (c = 0; c < m.nc; ++c) q[c] = U[c * N + k];
         cons_to_prim(&m, q, w, &r, &rc2);
+        if (m.nc == 7) out[6 * N + k] = w[6];
         out[k] = w[0] + w[1];
         out[N + k] = w[2];
         out[2 * N + k] = w[3];
@@ -484,7 +506,7 @@ double or_max_speed(const or_problem *P, const double *U)
     for (k = 0; k < N; ++k) {
         double q[NV], w[NV], r, rc2, c, s;
         int cc;
-        for (cc = 0; cc < NV; ++cc) q[cc] = U[cc * N + k];
+        for (cc = 0; cc < m.nc; ++cc) q[cc] = U[cc * N + k];
         cons_to_prim(&m, q, w, &r, &rc2);
         c = sqrt(rc2 * r);
         s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
@@ -494,12 +516,52 @@ double or_max_speed(const or_problem *P, const double *U)
     return bad ? NAN : smax;
 }
 
-/* One full time step with time-step size dt: split sweeps in the order set by
- * the parity of the step index, then the pointwise stage.  tmp: 6 N doubles. */
+/* Pointwise source stage of the Strang split (Sec. 3) over a time h, for the
+ * reactive liquid: single-step Arrhenius kinetics (Eq. (6), Table 3),
+ * K = -lambda C exp(-Ta / T2), with the liquid temperature of Eq. (5)
+ * (T_ref,2 = 0, constant c_v,2 and Gamma_0,2) frozen over the stage, so that
+ * lambda <- lambda exp(-C exp(-Ta / T2) h) exactly; the liquid mass that
+ * reacts releases Q per unit mass into rho E (the source -z2 rho2 K Q of
+ * Eq. (1)).  Cells with no reactant or a non-positive temperature are left
+ * alone.                                                                    */
+static void react_cell(const or_problem *P, const mixc *m, double q[NV], double h)
+{
+    double w[NV], r, rc2, rho2, pref, eref, rdpref, T, k, lam_new;
+    if (!(q[6] > 0.0)) return;
+    cons_to_prim(m, q, w, &r, &rc2);
+    rho2 = q[1] / (1.0 - q[5]);
+    cc_reference(m, rho2, &pref, &eref, &rdpref);
+    T = (w[4] - pref) / (rho2 * P->cc_gamma0 * P->rx_cv2);
+    if (!(T > 0.0)) return;
+    k = P->rx_C * exp(-P->rx_Ta / T);
+    lam_new = w[6] * exp(-k * h);
+    q[4] = q[4] + P->rx_Q * (q[6] - q[1] * lam_new);
+    q[6] = q[1] * lam_new;
+}
+
+static void react_all(const or_problem *P, const mixc *m, double *U, double h)
+{
+    long N = (long)P->nx * P->ny, k;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < N; ++k) {
+        double q[NV];
+        int c;
+        for (c = 0; c < NV; ++c) q[c] = U[c * N + k];
+        react_cell(P, m, q, h);
+        U[4 * N + k] = q[4];
+        U[6 * N + k] = q[6];
+    }
+}
+
+/* One full time step with time-step size dt: S(dt/2), split sweeps in the
+ * order set by the parity of the step index, S(dt/2), where the pointwise
+ * stage S is the z1 clamp (then the reaction of a reactive liquid).
+ * tmp: as many planes as U.                                                 */
 void or_step(const or_problem *P, double *U, double *tmp, int64_t step, double dt)
 {
     mixc m = mix_constants(P);
     double lamx = dt / P->dx, lamy = dt / P->dy;
+    if (m.nc == 7) react_all(P, &m, U, 0.5 * dt);
     if ((step & 1) == 0) {
         sweep_x(P, &m, U, tmp, lamx);
         sweep_y(P, &m, tmp, U, lamy);
@@ -508,6 +570,7 @@ void or_step(const or_problem *P, double *U, double *tmp, int64_t step, double d
         sweep_x(P, &m, tmp, U, lamx);
     }
     clamp_z(P, U);
+    if (m.nc == 7) react_all(P, &m, U, 0.5 * dt);
 }
 
 /* Time-step size from the CFL condition, clipped so that the run ends exactly
@@ -537,7 +600,7 @@ int64_t or_run(const or_problem *P, double *U, int64_t step0, int64_t nsteps, do
                double t_end, double *last_dt)
 {
     long N = (long)P->nx * P->ny;
-    double *tmp = (double *)malloc((size_t)N * NV * sizeof(double));
+    double *tmp = (double *)malloc((size_t)N * (P->reactive ? 7 : 6) * sizeof(double));
     int64_t n;
     for (n = 0; n < nsteps; ++n) {
         double dt, tn;
@@ -552,26 +615,27 @@ int64_t or_run(const or_problem *P, double *U, int64_t step0, int64_t nsteps, do
 }
 
 /* Updated state after one step at a list of cells only (for checking very
- * large grids cell by cell).  U: state before the step, all 6 planes.
- * cells[k] = j * nx + i.  out: 6 * ncells (component-major).                */
+ * large grids cell by cell).  U: state before the step, all planes.
+ * cells[k] = j * nx + i.  out: nc * ncells (component-major).               */
 static void sweep_point(const mixc *m, double win[NV][5], double lam, int limiter,
                         double qo[NV])
 {
     /* win[c][k]: cells -2..2 of a line-frame window centred on the target */
-    double W[5][NV], r[5], rc2[5], WL[3][NV], WH[3][NV], flo[7], fhi[7], q[NV];
+    double W[5][NV], r[5], rc2[5], WL[3][NV], WH[3][NV], flo[8], fhi[8], q[NV];
     int k, c;
     double hl = 0.5 * lam;
     for (k = 0; k < 5; ++k) {
         double qq[NV];
-        for (c = 0; c < NV; ++c) qq[c] = win[c][k];
+        for (c = 0; c < m->nc; ++c) qq[c] = win[c][k];
         cons_to_prim(m, qq, W[k], &r[k], &rc2[k]);
     }
     for (k = 1; k <= 3; ++k)
-        face_states(W[k - 1], W[k], W[k + 1], r[k], rc2[k], hl, limiter, WL[k - 1], WH[k - 1]);
+        face_states(W[k - 1], W[k], W[k + 1], r[k], rc2[k], hl, limiter, m->nc, WL[k - 1],
+                    WH[k - 1]);
     hllc(m, WH[0], WL[1], flo);
     hllc(m, WH[1], WL[2], fhi);
-    for (c = 0; c < NV; ++c) q[c] = win[c][2];
-    update_cell(q, flo, fhi, lam, qo);
+    for (c = 0; c < m->nc; ++c) q[c] = win[c][2];
+    update_cell(q, flo, fhi, lam, m->nc, qo);
 }
 
 static void xpoint(const or_problem *P, const mixc *m, const double *U, long i, long j,
@@ -582,7 +646,7 @@ static void xpoint(const or_problem *P, const mixc *m, const double *U, long i, 
     int k, c;
     for (k = 0; k < 5; ++k) {
         long ii = map_index(i + k - 2, nx, P->bc_xlo, P->bc_xhi);
-        for (c = 0; c < NV; ++c) win[c][k] = U[c * N + j * nx + ii];
+        for (c = 0; c < m->nc; ++c) win[c][k] = U[c * N + j * nx + ii];
     }
     sweep_point(m, win, lam, P->limiter, qo);
 }
@@ -595,19 +659,26 @@ static void ypoint(const or_problem *P, const mixc *m, const double *U, long i, 
     int k, c;
     for (k = 0; k < 5; ++k) {
         long jj = map_index(j + k - 2, ny, P->bc_ylo, P->bc_yhi);
-        for (c = 0; c < NV; ++c) win[c][k] = U[ymap[c] * N + jj * nx + i];
+        for (c = 0; c < m->nc; ++c) win[c][k] = U[ymap[c] * N + jj * nx + i];
     }
     sweep_point(m, win, lam, P->limiter, t);
-    for (c = 0; c < NV; ++c) qo[ymap[c]] = t[c];
+    for (c = 0; c < m->nc; ++c) qo[ymap[c]] = t[c];
 }
 
 void or_step_cells(const or_problem *P, const double *U, int64_t step, double dt,
                    const int64_t *cells, int64_t ncells, double *out)
 {
     mixc m = mix_constants(P);
-    long nx = P->nx, ny = P->ny;
+    long nx = P->nx, ny = P->ny, N = (long)P->nx * P->ny;
     double lamx = dt / P->dx, lamy = dt / P->dy;
+    double *Ur = NULL;
     int64_t s;
+    if (m.nc == 7) {   /* first half of the source stage on the whole state */
+        Ur = (double *)malloc((size_t)N * 7 * sizeof(double));
+        memcpy(Ur, U, (size_t)N * 7 * sizeof(double));
+        react_all(P, &m, Ur, 0.5 * dt);
+        U = Ur;
+    }
     for (s = 0; s < ncells; ++s) {
         long i = (long)(cells[s] % nx), j = (long)(cells[s] / nx);
         double mid[NV][5];   /* intermediate state on the 5-cell cross line */
@@ -618,16 +689,16 @@ void or_step_cells(const or_problem *P, const double *U, int64_t step, double dt
             for (k = 0; k < 5; ++k) {
                 long jj = map_index(j + k - 2, ny, P->bc_ylo, P->bc_yhi);
                 xpoint(P, &m, U, i, jj, lamx, win_t);
-                for (c = 0; c < NV; ++c) mid[ymap[c]][k] = win_t[c];
+                for (c = 0; c < m.nc; ++c) mid[ymap[c]][k] = win_t[c];
             }
             sweep_point(&m, mid, lamy, P->limiter, win_t);
-            for (c = 0; c < NV; ++c) qo[ymap[c]] = win_t[c];
+            for (c = 0; c < m.nc; ++c) qo[ymap[c]] = win_t[c];
         } else {
             /* Y first: intermediate values along row j, columns i-2..i+2 */
             for (k = 0; k < 5; ++k) {
                 long ii = map_index(i + k - 2, nx, P->bc_xlo, P->bc_xhi);
                 ypoint(P, &m, U, ii, j, lamy, win_t);
-                for (c = 0; c < NV; ++c) mid[c][k] = win_t[c];
+                for (c = 0; c < m.nc; ++c) mid[c][k] = win_t[c];
             }
             sweep_point(&m, mid, lamx, P->limiter, qo);
         }
@@ -635,8 +706,10 @@ void or_step_cells(const or_problem *P, const double *U, int64_t step, double dt
             double lo = P->zeps, hi = 1.0 - P->zeps;
             qo[5] = fmin(fmax(qo[5], lo), hi);
         }
-        for (c = 0; c < NV; ++c) out[c * ncells + s] = qo[c];
+        if (m.nc == 7) react_cell(P, &m, qo, 0.5 * dt);
+        for (c = 0; c < m.nc; ++c) out[c * ncells + s] = qo[c];
     }
+    free(Ur);
 }
 
 /* Temperature of the liquid from the linearisation about its reference curve
@@ -670,10 +743,10 @@ void or_unit_face_states(const double wm[NV], const double w0[NV], const double 
                          double r, double rc2, double hl, int32_t limiter, double wl[NV],
                          double wh[NV])
 {
-    face_states(wm, w0, wp, r, rc2, hl, limiter, wl, wh);
+    face_states(wm, w0, wp, r, rc2, hl, limiter, 6, wl, wh);
 }
 
-void or_unit_hllc(const or_problem *P, const double wL[NV], const double wR[NV], double out[7])
+void or_unit_hllc(const or_problem *P, const double wL[NV], const double wR[NV], double out[8])
 {
     mixc m = mix_constants(P);
     hllc(&m, wL, wR, out);
@@ -687,7 +760,7 @@ void or_unit_sweep_line(const or_problem *P, int64_t n, const double *qin, doubl
     double *qi[NV], *qo[NV];
     double *work = (double *)malloc(line_work_doubles(n) * sizeof(double));
     int c;
-    for (c = 0; c < NV; ++c) {
+    for (c = 0; c < m.nc; ++c) {
         qi[c] = (double *)qin + c * n;
         qo[c] = qout + c * n;
     }
@@ -713,7 +786,7 @@ static void cell_prim(const mixc *m, const double *U, long N, long k, double *p,
 {
     double q[NV], w[NV], r, rc2;
     int c;
-    for (c = 0; c < NV; ++c) q[c] = U[c * N + k];
+    for (c = 0; c < m->nc; ++c) q[c] = U[c * N + k];
     cons_to_prim(m, q, w, &r, &rc2);
     *p = w[4];
     *rho = q[0] + q[1];
@@ -744,14 +817,15 @@ void or_y_averages(const or_problem *P, const double *U, double *pbar, double *r
 }
 
 /* Domain integrals (cell area dx*dy): z1 rho1, z2 rho2, rho u, rho v, rho E,
- * air volume z1.  Each is (sum over i of (sum over j of q)) * area, both sums
- * in increasing index order.                                                */
-void or_integrals(const or_problem *P, const double *U, double out[6])
+ * air volume z1 and, for a reactive liquid, the remaining reactant mass
+ * M_2,r of Eq. (10).  Each is (sum over i of (sum over j of q)) * area, both
+ * sums in increasing index order.                                           */
+void or_integrals(const or_problem *P, const double *U, double out[7])
 {
     long nx = P->nx, ny = P->ny, N = nx * ny, i, j;
-    int c;
+    int c, nc = P->reactive ? 7 : 6;
     double area = P->dx * P->dy;
-    for (c = 0; c < 6; ++c) {
+    for (c = 0; c < nc; ++c) {
         double tot = 0.0;
         for (i = 0; i < nx; ++i) {
             double s = 0.0;
@@ -769,9 +843,24 @@ void or_log_edges(double lo, double dn, int32_t nbins, double *edges)
     for (k = 0; k <= nbins; ++k) edges[k] = pow(10.0, lo + (double)k * dn);
 }
 
-/* Mass-weighted histogram of pressure (field 9) or density (field 6) over
- * the log-spaced bins: m_k = sum of z2 rho2 dx dy over cells with
- * edges[k] <= v < edges[k+1];  f_k = m_k / (m_ref dn).                       */
+/* Volumetric rate of energy release q = -z2 rho2 K Q of the reactive liquid
+ * (Sec. 4.5), in GW/m^3, with the temperature of Eq. (5).                   */
+static double heat_release(const or_problem *P, const mixc *m, const double q[NV])
+{
+    double w[NV], r, rc2, rho2, pref, eref, rdpref, T;
+    if (!(q[6] > 0.0)) return 0.0;
+    cons_to_prim(m, q, w, &r, &rc2);
+    rho2 = q[1] / (1.0 - q[5]);
+    cc_reference(m, rho2, &pref, &eref, &rdpref);
+    T = (w[4] - pref) / (rho2 * P->cc_gamma0 * P->rx_cv2);
+    if (!(T > 0.0)) return 0.0;
+    return ((q[6] * P->rx_C) * exp(-P->rx_Ta / T) * P->rx_Q) * 1.0e-9;
+}
+
+/* Mass-weighted histogram of pressure (field 9), density (field 6) or the
+ * heat-release rate (field 14, GW/m^3) over the log-spaced bins:
+ * m_k = sum of z2 rho2 dx dy over cells with edges[k] <= v < edges[k+1];
+ * f_k = m_k / (m_ref dn)  (Sec. 4.5).                                        */
 void or_log_histogram(const or_problem *P, const double *U, int32_t field, double lo, double dn,
                       int32_t nbins, double m_ref, double *f)
 {
@@ -785,8 +874,15 @@ void or_log_histogram(const or_problem *P, const double *U, int32_t field, doubl
     for (k = 0; k < N; ++k) {
         double p, rho, mu, v;
         int32_t a, z;
-        cell_prim(&m, U, N, k, &p, &rho, &mu);
-        v = (field == 6) ? rho : p;
+        if (field == 14) {
+            double q[NV];
+            int c;
+            for (c = 0; c < m.nc; ++c) q[c] = U[c * N + k];
+            v = heat_release(P, &m, q);
+        } else {
+            cell_prim(&m, U, N, k, &p, &rho, &mu);
+            v = (field == 6) ? rho : p;
+        }
         if (!(v >= edges[0]) || !(v < edges[nbins])) continue;
         /* largest a with edges[a] <= v */
         a = 0;

@@ -37,6 +37,10 @@ SEEDS = {"random_4096x2048": 1905, "roofline_8192": 5727, "serving": 2019}
 NM_CC = (1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0)
 NM_CV = 1714.0
 RHO_NM = 1134.0           # Sec. 2.4
+# Arrhenius kinetics of liquid nitromethane (Eq. (6), Table 3): pre-exponential
+# factor C [1/s], activation temperature Ta [K], heat of reaction Q [J/kg];
+# with c_v,2 [J/(kg K)] of Table 1 for the temperature of Eq. (5).
+NM_RX = (2.6e9, 11350.0, 4.46e6, NM_CV)
 
 
 @dataclass
@@ -60,6 +64,8 @@ class Scenario:
     t_end: float = 0.0                    # end time of the workload (0: none)
     eos2: int = 0                         # liquid EoS: 0 stiffened gas, 1 Cochran-Chan
     cc: tuple = NM_CC                     # Cochran-Chan parameters when eos2 == 1
+    reactive: bool = False                # 7th plane: reaction progress lambda
+    rx: tuple = NM_RX
     meta: dict = field(default_factory=dict)
 
 
@@ -171,6 +177,19 @@ def _finish(prim: np.ndarray, eps: float) -> np.ndarray:
     return prim
 
 
+def make_reactive(sc: Scenario, strip: int) -> Scenario:
+    """Add the reaction progress variable as a 7th primitive plane: lambda = 1
+    (unreacted liquid) everywhere except the initially shocked region, where it
+    is 0 so that the shocked liquid releases no energy (Sec. 2.4).  Requires
+    the Cochran-Chan liquid."""
+    assert sc.eos2 == 1, "the reactive model is defined for the Cochran-Chan liquid"
+    lam = np.ones((1, sc.ny, sc.nx))
+    lam[0, :, :strip] = 0.0
+    sc.prim = np.concatenate([sc.prim, lam], axis=0)
+    sc.reactive = True
+    return sc
+
+
 def place_bubbles(rng: np.random.Generator, n: int, nx: int, ny: int, rmin: float,
                   rmax: float, gap: float, x_lo: float, max_draws: int = 1_000_000):
     """Seeded rejection sampling of n non-overlapping circles (cell units).
@@ -236,17 +255,19 @@ def shock_tube_1d(nx: int = 1000, ny: int = 1, x0: float = 0.7, length: float = 
 
 def single_bubble(nx: int = 1024, ny: int = 512, dx: float = 1.0e-5, radius: float = 64.0,
                   centre=(400.0, 256.0), shock_x: float = 320.0, p_shock: float = 1.0e9,
-                  steps: int = 2000, eps: float = Z_EPS, liquid: str = "water") -> Scenario:
+                  steps: int = 2000, eps: float = Z_EPS, liquid: str = "water",
+                  reactive: bool = False) -> Scenario:
     """One air bubble in water hit by a planar 1 GPa shock; the shocked water
     occupies x < shock_x (cell units).  Mirror symmetric about y = ny/2 when
     the centre lies on it."""
     prim = _blank(nx, ny)
     (rho1, u1, S), kw = _liquid(prim, liquid, p_shock, int(shock_x))
     _paint_bubble(prim[0], centre[0], centre[1], radius)
-    return Scenario("single_bubble", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
-                    steps=steps, meta=dict(p_shock=p_shock, shock_speed=S, rho1=rho1, u1=u1,
-                                           radius=radius, centre=centre, shock_x=shock_x,
-                                           liquid=liquid), **kw)
+    sc = Scenario("single_bubble", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                  steps=steps, meta=dict(p_shock=p_shock, shock_speed=S, rho1=rho1, u1=u1,
+                                         radius=radius, centre=centre, shock_x=shock_x,
+                                         liquid=liquid), **kw)
+    return make_reactive(sc, int(shock_x)) if reactive else sc
 
 
 def random_bubbles(nx: int, ny: int, nbubbles: int, rmin: float, rmax: float, gap: float,
@@ -350,7 +371,7 @@ def _liquid(prim: np.ndarray, liquid: str, p_shock: float, strip: int):
 
 def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip: int = 500,
                   p_shock: float = 1.0e9, dx: float = 1.0e-6, eps: float = Z_EPS,
-                  steps: int = 0, liquid: str = "water") -> Scenario:
+                  steps: int = 0, liquid: str = "water", reactive: bool = False) -> Scenario:
     """Square array of equal cavities (Sec. 2.4, Fig. 1(b)): spacing from
     Eq. (6_1), domain width = one spacing with periodic top/bottom walls, a
     shocked strip of `strip` cells at the transmissive left wall."""
@@ -366,17 +387,18 @@ def regular_array(d_c: int = 100, phi: float = 0.08, length: int = 24000, strip:
         _paint_bubble_periodic_y(prim[0], x, 0.5 * ny, R)
         centres.append((x, 0.5 * ny, R))
         x += delta
-    return Scenario("regular_array", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
-                    bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
-                    meta=dict(spacing=delta, ncavities=len(centres), p_shock=p_shock,
-                              shock_speed=S, bubbles=np.array(centres), liquid=liquid), **kw)
+    sc = Scenario("regular_array", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                  bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
+                  meta=dict(spacing=delta, ncavities=len(centres), p_shock=p_shock,
+                            shock_speed=S, bubbles=np.array(centres), liquid=liquid), **kw)
+    return make_reactive(sc, strip) if reactive else sc
 
 
 def random_cavities(d_c: int = 100, phi: float = 0.08, length: int = 24000, width: int = 2000,
                     strip: int = 500, min_spacing: float = 2.5, p_shock: float = 1.0e9,
                     dx: float = 1.0e-6, seed: int = 1905, eps: float = Z_EPS,
                     steps: int = 0, max_draws: int = 2_000_000,
-                    liquid: str = "water") -> Scenario:
+                    liquid: str = "water", reactive: bool = False) -> Scenario:
     """Random field of equal cavities (Sec. 2.4, Fig. 1(c)): the count from
     Eq. (7) over the region ahead of the shocked strip, centres uniform with a
     minimum centre-to-centre distance of `min_spacing` diameters (Sec. 3),
@@ -408,10 +430,11 @@ def random_cavities(d_c: int = 100, phi: float = 0.08, length: int = 24000, widt
     for x, y in zip(xs, ys):
         _paint_bubble_periodic_y(prim[0], x, y, R)
     cen = np.stack([xs, ys, np.full(ncav, R)], axis=1)
-    return Scenario("random_cavities", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
-                    bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
-                    meta=dict(seed=seed, ncavities=ncav, porosity_target=phi, p_shock=p_shock,
-                              shock_speed=S, bubbles=cen, nbubbles=ncav, liquid=liquid), **kw)
+    sc = Scenario("random_cavities", nx, ny, dx, dx, _finish(prim, eps), cfl=0.4,
+                  bc=("transmissive", "transmissive", "periodic", "periodic"), steps=steps,
+                  meta=dict(seed=seed, ncavities=ncav, porosity_target=phi, p_shock=p_shock,
+                            shock_speed=S, bubbles=cen, nbubbles=ncav, liquid=liquid), **kw)
+    return make_reactive(sc, strip) if reactive else sc
 
 
 def uniform_state(nx: int, ny: int, dx: float = 1.0e-3, z1: float = Z_EPS,
