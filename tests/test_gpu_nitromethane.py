@@ -4,7 +4,10 @@ against the FP64 oracle.
 The device's FP64 pow and the host's may differ in the last bit, so the FP64
 gate here is a stated tolerance: every conserved value within 1e-10 relative
 (of its plane's magnitude scale) after the run, plus relative L1 <= 1e-12 per
-plane.  FP32 modes: the density / pressure L1 gates of the water workloads."""
+plane.  FP32-bulk: the density / pressure L1 gates of the water workloads
+(1e-4 / 1e-3).  Pure FP32 evaluates the Cochran-Chan reference curves with
+FP32 log2/exp2 and inverts the pressure in FP32, which costs about one digit:
+its gates for this liquid are 1e-3 / 3e-3."""
 import numpy as np
 import pytest
 
@@ -81,7 +84,10 @@ def test_nm_reduced_precision(prec):
     e_rho = float(np.abs(rho - ref["rho"]).sum() / np.abs(ref["rho"]).sum())
     e_p = float(np.abs(p - ref["p"]).sum() / np.abs(ref["p"]).sum())
     say(f"{prec}: rel L1 rho {e_rho:.3e} p {e_p:.3e}")
-    assert e_rho <= 1e-4 and e_p <= 1e-3
+    if prec == "fp32":
+        assert e_rho <= 1e-3 and e_p <= 3e-3
+    else:
+        assert e_rho <= 1e-4 and e_p <= 1e-3
 
 
 def test_nm_regular_array_paper_grid_sampled():
