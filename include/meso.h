@@ -9,7 +9,10 @@
  * air as an ideal gas, Table 2).  The scheme is that of Sec. 3:
  * MUSCL-Hancock reconstruction with a van Leer (or minmod) slope limiter, HLLC
  * fluxes, dimensionally split sweeps, a CFL time step, and the pointwise stage
- * of the Strang split (with no reaction: z1 kept in [eps, 1 - eps]).
+ * of the Strang split (z1 kept in [eps, 1 - eps]; for a reactive liquid also
+ * the single-step Arrhenius reaction of Eq. (6) at the liquid temperature of
+ * Eq. (5), with the reactant mass z2 rho2 lambda of Eq. (1) as a seventh
+ * conserved component).
  *
  * The calls follow the paper's statement of the problem (Sec. 2.4 and Sec. 3):
  * a rectangular uniform grid with two materials, initial fields set once,
@@ -25,7 +28,10 @@
  *  - Field arrays are planes of nx*ny doubles, row-major with x fastest
  *    (index j*nx + i).  Primitive sets are 6 consecutive planes
  *    (z1, rho1, rho2, u, v, p); conserved sets are 6 consecutive planes
- *    (z1 rho1, z2 rho2, rho u, rho v, rho E, z1).
+ *    (z1 rho1, z2 rho2, rho u, rho v, rho E, z1).  A reactive solver (liquid
+ *    material with reactive = 1) has a seventh plane in both: the reaction
+ *    progress lambda (primitive; the liquid's unreacted mass fraction, 1 =
+ *    fresh) and the reactant mass z2 rho2 lambda (conserved).
  *  - Stepping calls only enqueue work on the solver's stream and return;
  *    errors found on the device (non-finite state, rho <= 0, rho c^2 <= 0)
  *    are latched and reported by the next synchronising call
@@ -81,6 +87,14 @@ extern "C" {
 #define MF_V      8
 #define MF_P      9
 #define MF_C     10
+/* Reactive solvers only: the seventh conserved plane, the reaction progress
+ * lambda, the liquid temperature of Eq. (5) (K) and the volumetric
+ * heat-release rate -z2 rho2 K Q of Sec. 4.5 (GW/m^3, 0 where there is no
+ * reactant or T <= 0). */
+#define MF_Z2RHO2LAM 11
+#define MF_LAMBDA    12
+#define MF_T2        13
+#define MF_QDOT      14
 
 /* Equation of state of a phase, in the Mie-Grueneisen form of Eq. (2),
  * p = p_ref(rho) + rho Gamma (e - e_ref(rho)):
@@ -88,16 +102,23 @@ extern "C" {
  *                       terms; air: the ideal gas, p_inf = 0);
  *  MF_EOS_COCHRAN_CHAN: Gamma = gamma0, p_ref and e_ref of Eqs. (3)-(4) with
  *                       the constants A, B (Pa), C, D and rho0 (Table 1).
- *  Phase 1 (the gas) must be MF_EOS_STIFFENED. */
+ *  Phase 1 (the gas) must be MF_EOS_STIFFENED.
+ * reactive = 1 (phase 2 only, MF_EOS_COCHRAN_CHAN only) makes the liquid an
+ * explosive: single-step Arrhenius kinetics d lambda/dt = -lambda C exp(-Ta/T)
+ * (Eq. (6); C = arr_C in 1/s, Ta = arr_Ta in K, Table 3) releasing heat_Q
+ * J/kg (Table 3) into rho E, at the liquid temperature
+ * T = (p - p_ref(rho2)) / (rho2 gamma0 cv) of Eq. (5) (cv in J/(kg K),
+ * Table 1; reference temperature 0 K).  Unused members are ignored. */
 #define MF_EOS_STIFFENED     0
 #define MF_EOS_COCHRAN_CHAN  1
 
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t reactive;
     double gamma;
     double p_inf;
     double gamma0, A, B, C, D, rho0;
+    double cv, arr_C, arr_Ta, heat_Q;
 } mf_material;
 
 /* Uniform Cartesian grid (Sec. 3), cell sizes in metres. */
@@ -122,9 +143,11 @@ typedef struct {
 
 typedef struct mf_solver mf_solver;
 
-/* Device bytes a solver of this grid and precision needs (two state copies
- * plus a 256-byte control block).  0 for an invalid grid. */
-size_t mf_workspace_bytes(const mf_grid *grid, int32_t precision);
+/* Device bytes a solver of this grid, materials and precision needs (two
+ * state copies of 6 planes -- 7 if the liquid is reactive -- plus a 256-byte
+ * control block).  mat may be NULL (an inert pair).  0 for an invalid grid,
+ * precision or material pair. */
+size_t mf_workspace_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision);
 
 /* Create a solver on the current HIP device.
  *  mat[0] = phase 1 (gas, the cavity content), mat[1] = phase 2 (liquid).
@@ -139,12 +162,13 @@ int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_option
                   void *dev_workspace, size_t ws_bytes, void *hip_stream, mf_solver **out);
 
 /* Set the state from host primitive planes (z1, rho1, rho2, u, v, p), 6*nx*ny
- * doubles, converted to conserved variables on the device by the closure of
- * Sec. 2.1.  Resets the latched error and computes the first time step's CFL
+ * doubles (7*nx*ny with lambda last for a reactive solver), converted to
+ * conserved variables on the device by the closure of Sec. 2.1.  Resets the latched error and computes the first time step's CFL
  * bound.  Synchronises the stream.  Time and step count are unchanged. */
 int32_t mf_set_primitive(mf_solver *s, const double *prim);
 
-/* Set the state from host conserved planes (6*nx*ny doubles); in MF_FP32 mode
+/* Set the state from host conserved planes (6*nx*ny doubles, 7*nx*ny for a
+ * reactive solver); in MF_FP32 mode
  * the values are rounded to float.  Same side effects as mf_set_primitive. */
 int32_t mf_set_conserved(mf_solver *s, const double *cons);
 
@@ -173,7 +197,8 @@ int32_t mf_sync(mf_solver *s);
  * nx*ny).  Derived fields use the closure of Sec. 2.1.  Synchronises. */
 int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t count);
 
-/* Copy the 6 conserved planes (6*nx*ny doubles) to host_out.  Synchronises. */
+/* Copy the conserved planes (6*nx*ny doubles, 7*nx*ny for a reactive solver)
+ * to host_out; count must be that size.  Synchronises. */
 int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count);
 
 /* Time, completed step count and the last time step.  Synchronises. */
@@ -188,13 +213,15 @@ int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt);
  *   u_bar = (1/(W rho_bar)) int rho u dy (density-weighted). */
 int32_t mf_y_averages(mf_solver *s, double *p_bar, double *rho_bar, double *u_bar, size_t nx);
 
-/* Domain integrals over the grid (cell area dx*dy), count must be 6:
- *   z1 rho1, z2 rho2, rho u, rho v, rho E and the gas volume z1. */
+/* Domain integrals over the grid (cell area dx*dy), count must be 6 (7 for a
+ * reactive solver): z1 rho1, z2 rho2, rho u, rho v, rho E, the gas volume z1
+ * and the remaining reactant mass M_2,r of Eq. (10). */
 int32_t mf_integrals(mf_solver *s, double *out, size_t count);
 
 /* Mass-weighted probability density on log-spaced bins (Sec. 4.5): bin k
- * covers 10^(lo + k dn) <= v < 10^(lo + (k+1) dn) of the field v (MF_P or
- * MF_RHO), collects the liquid mass z2 rho2 dx dy of its cells, and
+ * covers 10^(lo + k dn) <= v < 10^(lo + (k+1) dn) of the field v (MF_P,
+ * MF_RHO, or MF_QDOT of a reactive solver), collects the liquid mass
+ * z2 rho2 dx dy of its cells, and
  * f_out[k] = m_k / (m_ref dn).  1 <= nbins <= 1024, dn > 0, m_ref > 0. */
 int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
                          double m_ref, double *f_out);
@@ -267,11 +294,12 @@ size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision);
  * MF_E_OUT_OF_MEMORY (arena allocation), MF_E_DEVICE. */
 int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_server **out);
 
-/* Queue one solve: grid, materials (gas, liquid), options (cfl, z_floor;
- * limiter and precision must equal the server's; fused is ignored), host
- * primitive planes (6*nx*ny doubles, copied during the call) and the number
- * of CFL steps to take (>= 1).  *ticket receives the request id.
- * MF_E_OUT_OF_MEMORY if the request can never fit in the budget. */
+/* Queue one solve: grid, materials (gas, liquid; inert only -- a reactive
+ * liquid gives MF_E_INVALID_ARG), options (cfl, z_floor; limiter and
+ * precision must equal the server's; fused is ignored), host primitive planes
+ * (6*nx*ny doubles, copied during the call) and the number of CFL steps to
+ * take (>= 1).  *ticket receives the request id.  MF_E_OUT_OF_MEMORY if the
+ * request can never fit in the budget. */
 int32_t mf_server_submit(mf_server *srv, const mf_grid *grid, const mf_material mat[2],
                          const mf_options *opt, const double *prim, int64_t nsteps,
                          uint64_t *ticket);

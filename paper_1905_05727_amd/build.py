@@ -1,10 +1,10 @@
 """Build step of the HIP library (hipcc, gfx950).
 
-The shared library libmeso.so is built in-tree next to this file from four
-translation units.  The FP64 kernels and the host code are compiled with
--ffp-contract=off (every operation rounds separately, so the FP64 mode
-follows the arithmetic contract bit for bit); the FP32-bulk / FP32 kernels
-with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
+The shared library libmeso.so is built in-tree next to this file from six
+translation units, compiled in parallel.  The FP64 kernels and the host code
+are compiled with -ffp-contract=off (every operation rounds separately, so
+the FP64 mode follows the arithmetic contract bit for bit); the FP32-bulk /
+FP32 kernels with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
 packed FP32 instructions are disabled (-packed-fp32-ops).
 """
 from __future__ import annotations
@@ -22,6 +22,7 @@ ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 
 # (source, floating-point contraction)
 UNITS = [("meso_kernels.hip", "off"), ("meso_kernels_fast.hip", "fast"),
+         ("meso_kernels_react.hip", "off"), ("meso_kernels_react_fast.hip", "fast"),
          ("meso_api.hip", "off"), ("meso_server.hip", "off")]
 
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fno-fast-math",
@@ -31,17 +32,21 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fno-fast-mat
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link libmeso.so (always recompiles)."""
+    """Compile every HIP source (in parallel) and link libmeso.so (always
+    recompiles)."""
     with tempfile.TemporaryDirectory(prefix="meso_build_") as tmp:
-        objs = []
+        jobs = []
         for src, contract in UNITS:
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             cmd = [HIPCC, *COMMON, f"-ffp-contract={contract}", "-c", "-o", obj,
                    os.path.join(CSRC, src)]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
-            objs.append(obj)
+            jobs.append((obj, subprocess.Popen(cmd)))
+        failed = [obj for obj, p in jobs if p.wait() != 0]
+        if failed:
+            raise RuntimeError("hipcc failed for " + ", ".join(os.path.basename(f) for f in failed))
+        objs = [obj for obj, _ in jobs]
         out = LIB + ".tmp"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out, *objs]
         if verbose:

@@ -34,6 +34,14 @@ bool valid_grid(const mf_grid *g) {
 
 bool valid_materials(const mf_material *mat) {
     if (!mat) return false;
+    if (mat[0].reactive != 0 || (mat[1].reactive != 0 && mat[1].reactive != 1)) return false;
+    if (mat[1].reactive) {
+        const mf_material &m = mat[1];
+        if (m.kind != MF_EOS_COCHRAN_CHAN || !(m.cv > 0.0) || !isfinite(m.cv) ||
+            !(m.arr_C > 0.0) || !isfinite(m.arr_C) || !(m.arr_Ta >= 0.0) ||
+            !isfinite(m.arr_Ta) || !(m.heat_Q >= 0.0) || !isfinite(m.heat_Q))
+            return false;
+    }
     for (int k = 0; k < 2; ++k) {
         if (mat[k].kind == MF_EOS_STIFFENED) {
             if (!(mat[k].gamma > 1.0) || !isfinite(mat[k].gamma) || !(mat[k].p_inf >= 0.0) ||
@@ -61,9 +69,11 @@ bool valid_scheme(const mf_options *opt) {
     return true;
 }
 
-size_t state_bytes(const mf_grid *g, int prec) {
+int planes_of(const mf_material *mat) { return (mat && mat[1].reactive == 1) ? 7 : 6; }
+
+size_t state_bytes(const mf_grid *g, int prec, int nc) {
     const size_t es = prec == MF_FP32 ? 4 : 8;
-    return round_up((size_t)6 * pitch_of(g->nx) * (size_t)g->ny * es, kAlign);
+    return round_up((size_t)nc * pitch_of(g->nx) * (size_t)g->ny * es, kAlign);
 }
 
 int choose_seg_h(int nstrips, int ny) {
@@ -81,7 +91,8 @@ void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_optio
                char *base, int seg_h) {
     d.ctl = (Control *)base;
     d.buf[0] = base + kAlign;
-    d.buf[1] = base + kAlign + state_bytes(g, opt->precision);
+    d.nc = planes_of(mat);
+    d.buf[1] = base + kAlign + state_bytes(g, opt->precision, d.nc);
     d.nx = g->nx;
     d.ny = g->ny;
     d.pitch = pitch_of(g->nx);
@@ -117,10 +128,20 @@ void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_optio
         d.ckB = m.B / (m.rho0 * (1.0 - m.D));
         d.cAC = m.A * m.C;
         d.cBD = m.B * m.D;
+        d.cG0 = m.gamma0;
     } else {
         d.g2 = 1.0 / (mat[1].gamma - 1.0);
         d.h2 = (mat[1].gamma * mat[1].p_inf) * d.g2;
         d.ciG = d.cA = d.cB = d.cC = d.cD = d.crho0 = d.ckA = d.ckB = d.cAC = d.cBD = 0.0;
+        d.cG0 = 0.0;
+    }
+    if (d.nc == 7) {
+        d.rxcv = mat[1].cv;
+        d.rxC = mat[1].arr_C;
+        d.rxTa = mat[1].arr_Ta;
+        d.rxQ = mat[1].heat_Q;
+    } else {
+        d.rxcv = d.rxC = d.rxTa = d.rxQ = 0.0;
     }
 }
 
@@ -218,9 +239,10 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
 
 extern "C" {
 
-size_t mf_workspace_bytes(const mf_grid *grid, int32_t precision) {
+size_t mf_workspace_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision) {
     if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
-    return kAlign + 2 * state_bytes(grid, precision);
+    if (mat && !meso::valid_materials(mat)) return 0;
+    return kAlign + 2 * state_bytes(grid, precision, meso::planes_of(mat));
 }
 
 int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_options *opt,
@@ -230,7 +252,7 @@ int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_option
     if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt))
         return MF_E_INVALID_ARG;
     if (opt->fused != 0 && opt->fused != 1) return MF_E_INVALID_ARG;
-    const size_t need = mf_workspace_bytes(grid, opt->precision);
+    const size_t need = mf_workspace_bytes(grid, mat, opt->precision);
     if (dev_workspace && (ws_bytes < need || ((uintptr_t)dev_workspace % kAlign) != 0))
         return MF_E_INVALID_ARG;
 
@@ -275,7 +297,7 @@ static int32_t set_state(mf_solver *s, const double *host, bool prim) {
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    const size_t n = (size_t)s->grid.nx * s->grid.ny * 6;
+    const size_t n = (size_t)s->grid.nx * s->grid.ny * s->d.nc;
     double *tmp = nullptr;
     if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
@@ -303,7 +325,7 @@ int32_t mf_set_time(mf_solver *s, double t, int64_t step) {
     if (st != MF_OK) return st;
     const int from = state_index(s, c.step), to = state_index(s, step);
     if (from != to) {
-        const size_t b = state_bytes(&s->grid, s->opt.precision);
+        const size_t b = state_bytes(&s->grid, s->opt.precision, s->d.nc);
         if (hipMemcpyAsync(s->d.buf[to], s->d.buf[from], b, hipMemcpyDeviceToDevice,
                            s->stream) != hipSuccess)
             return MF_E_DEVICE;
@@ -359,7 +381,9 @@ int32_t mf_sync(mf_solver *s) {
 }
 
 int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t count) {
-    if (!s || !host_out || field < 0 || field > MF_C) return MF_E_INVALID_ARG;
+    if (!s || !host_out || field < 0) return MF_E_INVALID_ARG;
+    if (field > MF_C && !(s->d.nc == 7 && field >= MF_Z2RHO2LAM && field <= MF_QDOT))
+        return MF_E_INVALID_ARG;
     const size_t n = (size_t)s->grid.nx * s->grid.ny;
     if (count != n) return MF_E_INVALID_ARG;
     Control c;
@@ -382,22 +406,25 @@ int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t coun
 int32_t mf_read_conserved(mf_solver *s, double *host_out, size_t count) {
     if (!s || !host_out) return MF_E_INVALID_ARG;
     const size_t n = (size_t)s->grid.nx * s->grid.ny;
-    if (count != 6 * n) return MF_E_INVALID_ARG;
-    for (int f = 0; f < 6; ++f) {
-        int32_t st = mf_read_field(s, f, host_out + f * n, n);
+    const int nc = s->d.nc;
+    if (count != (size_t)nc * n) return MF_E_INVALID_ARG;
+    for (int f = 0; f < nc; ++f) {
+        int32_t st = mf_read_field(s, f < 6 ? f : MF_Z2RHO2LAM, host_out + f * n, n);
         if (st != MF_OK) return st;
     }
     return MF_OK;
 }
 
-// Column sums of the current state into a temporary device array (9 * nx).
+// Column sums of the current state into a temporary device array
+// ((3 + nc) * nx, then room for the nc integrals).
 static int32_t column_pass(mf_solver *s, double **cols_out) {
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
     if (c.err) return MF_E_NONFINITE_STATE;
     double *cols = nullptr;
-    if (hipMalloc(&cols, sizeof(double) * (9 * (size_t)s->grid.nx + 8)) != hipSuccess) {
+    if (hipMalloc(&cols, sizeof(double) * ((3 + (size_t)s->d.nc) * s->grid.nx + 8)) !=
+        hipSuccess) {
         (void)hipGetLastError();
         return MF_E_OUT_OF_MEMORY;
     }
@@ -427,21 +454,23 @@ int32_t mf_y_averages(mf_solver *s, double *p_bar, double *rho_bar, double *u_ba
 }
 
 int32_t mf_integrals(mf_solver *s, double *out, size_t count) {
-    if (!s || !out || count != 6) return MF_E_INVALID_ARG;
+    if (!s || !out || count != (size_t)s->d.nc) return MF_E_INVALID_ARG;
     double *cols = nullptr;
     int32_t st = column_pass(s, &cols);
     if (st != MF_OK) return st;
-    double *res = cols + 9 * (size_t)s->grid.nx;
+    double *res = cols + (3 + (size_t)s->d.nc) * s->grid.nx;
     hipError_t e = meso::launch_integrals(s->d, cols, res, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e == hipSuccess) e = hipMemcpy(out, res, 6 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(out, res, count * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(cols);
     return dev_err(e);
 }
 
 int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
                          double m_ref, double *f_out) {
-    if (!s || !f_out || (field != MF_P && field != MF_RHO) || nbins < 1 || nbins > 1024 ||
+    if (!s || !f_out ||
+        (field != MF_P && field != MF_RHO && !(field == MF_QDOT && s->d.nc == 7)) ||
+        nbins < 1 || nbins > 1024 ||
         !(dn > 0.0) || !isfinite(lo) || !isfinite(dn) || !(m_ref > 0.0))
         return MF_E_INVALID_ARG;
     Control c;

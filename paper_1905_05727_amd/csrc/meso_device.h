@@ -13,8 +13,10 @@
 // and the pointwise stage of the Strang split (z1 clamp when inert).
 //
 // Data layout in HBM: structure of arrays, 6 planes (z1 rho1, z2 rho2, rho u,
-// rho v, rho E, z1), rows padded to a multiple of 64 elements; two state copies
-// used as ping-pong buffers.
+// rho v, rho E, z1) -- 7 with the reactant mass z2 rho2 lambda of a reactive
+// liquid -- rows padded to a multiple of 64 elements; two state copies used as
+// ping-pong buffers.  NC (6 or 7) is the number of conserved components, a
+// template parameter so that the inert kernels carry no seventh component.
 //
 // Step kernel: a workgroup of 256 threads (4 wave64) owns a strip of 256
 // columns (252 written + 2 halo columns per side) and marches down a segment
@@ -57,6 +59,7 @@ template <> struct Ar<double, false> {
     static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
     static __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
     static __device__ __forceinline__ double big() { return 1.0e300; }
+    static __device__ __forceinline__ double ex(double a) { return exp(a); }
 };
 template <> struct Ar<double, true> {
     static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
@@ -73,6 +76,7 @@ template <> struct Ar<double, true> {
     static __device__ __forceinline__ double sqrt_(double a) { return __builtin_amdgcn_sqrt(a); }
     static __device__ __forceinline__ double rsq(double a) { return __builtin_amdgcn_rsq(a); }
     static __device__ __forceinline__ double big() { return 1.0e300; }
+    static __device__ __forceinline__ double ex(double a) { return exp(a); }
 };
 template <bool FAST> struct Ar<float, FAST> {
     static __device__ __forceinline__ void pw(float v, float C, float D, float &vc, float &vd) {
@@ -87,6 +91,9 @@ template <bool FAST> struct Ar<float, FAST> {
     static __device__ __forceinline__ float sqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
     static __device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
     static __device__ __forceinline__ float big() { return FLT_MAX; }
+    static __device__ __forceinline__ float ex(float a) {   // e^a = 2^(a log2 e)
+        return __builtin_amdgcn_exp2f(a * 1.44269504088896341f);
+    }
 };
 
 // Mixture constants: every phase in the Mie-Grueneisen form of Eq. (2),
@@ -107,6 +114,18 @@ template <class T> __device__ __forceinline__ Mix<T> mix_of(const Desc &d) {
     m.A = (T)d.cA; m.B = (T)d.cB; m.C = (T)d.cC; m.D = (T)d.cD; m.rho0 = (T)d.crho0;
     m.iG = (T)d.ciG; m.kA = (T)d.ckA; m.kB = (T)d.ckB; m.AC = (T)d.cAC; m.BD = (T)d.cBD;
     return m;
+}
+
+// Single-step Arrhenius kinetics of the reactive liquid (Eq. (6), Table 3)
+// and the constants of its temperature (Eq. (5)): Gamma_0 and c_v.
+template <class T> struct Rx {
+    T C, Ta, Q, G0, cv;
+};
+
+template <class T> __device__ __forceinline__ Rx<T> rx_of(const Desc &d) {
+    Rx<T> x;
+    x.C = (T)d.rxC; x.Ta = (T)d.rxTa; x.Q = (T)d.rxQ; x.G0 = (T)d.cG0; x.cv = (T)d.rxcv;
+    return x;
 }
 
 // Cochran-Chan liquid at partial density a2 and volume fraction z2:
@@ -137,9 +156,10 @@ __device__ __forceinline__ int map_idx(int i, int n, int bc_lo, int bc_hi) {
 
 // ------------------------------------------------------------------------
 // Closure (Sec. 2.1): sweep-frame conserved q = (a1, a2, mn, mt, E, z) to
-// primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2.
-template <class S, bool FAST>
-__device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[6], S &r,
+// primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2; with NC = 7 also
+// q[6] = z2 rho2 lambda to w[6] = lambda, the liquid's unreacted mass fraction.
+template <class S, bool FAST, int NC>
+__device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w[NC], S &r,
                                              S &rc2) {
     const S rho = q[0] + q[1];
     const S z = q[5];
@@ -170,6 +190,7 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[6], S w[
     if (m.eos2 == 1) rc2 = ((p * (S(1) + xi) + eta) - psi) * ixi;
     else rc2 = (p * (S(1) + xi) + eta) * ixi;
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
+    if constexpr (NC == 7) w[6] = Ar<S, FAST>::div(q[6], q[1]);
 }
 
 // Slope limiter (Sec. 3): a backward, b forward difference.
@@ -186,12 +207,12 @@ __device__ __forceinline__ R limit(R a, R b) {
 }
 
 // MUSCL reconstruction and Hancock half step in primitive variables.
-template <class R, bool FAST, int LIM>
-__device__ __forceinline__ void face_states(const R wm[6], const R w0[6], const R wp[6], R r,
-                                            R rc2, R hl, R wl[6], R wh[6]) {
-    R d[6], s[6];
+template <class R, bool FAST, int LIM, int NC>
+__device__ __forceinline__ void face_states(const R wm[NC], const R w0[NC], const R wp[NC], R r,
+                                            R rc2, R hl, R wl[NC], R wh[NC]) {
+    R d[NC], s[NC];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) d[c] = limit<R, FAST, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
+    for (int c = 0; c < NC; ++c) d[c] = limit<R, FAST, LIM>(w0[c] - wm[c], wp[c] - w0[c]);
     const R un = w0[2];
     s[0] = hl * (un * d[0] + w0[0] * d[2]);
     s[1] = hl * (un * d[1] + w0[1] * d[2]);
@@ -199,20 +220,24 @@ __device__ __forceinline__ void face_states(const R wm[6], const R w0[6], const 
     s[3] = hl * (un * d[3]);
     s[4] = hl * (un * d[4] + rc2 * d[2]);
     s[5] = hl * (un * d[5]);
+    if constexpr (NC == 7) s[6] = hl * (un * d[6]);   // lambda is advected
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < NC; ++c) {
         wl[c] = (w0[c] - R(0.5) * d[c]) - s[c];
         wh[c] = (w0[c] + R(0.5) * d[c]) - s[c];
     }
 }
 
-template <class R> struct Side {
+// Sweep-side state of a Riemann problem: conserved components U and fluxes F
+// (5 inert, a 6th for the reactant mass z2 rho2 lambda when NC = 7).
+template <class R, int NC> struct Side {
     R rho, un, ut, p, z, E;
-    R U[5], F[5];
+    R U[NC - 1], F[NC - 1];
 };
 
-template <class R, bool FAST>
-__device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R> &s, R &c) {
+template <class R, bool FAST, int NC>
+__device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[NC], Side<R, NC> &s,
+                                          R &c) {
     const R rho = w[0] + w[1];
     const R un = w[2], ut = w[3], p = w[4], z = w[5];
     const R z2 = R(1) - z;
@@ -238,10 +263,14 @@ __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[6], Side<R>
     s.F[2] = mn * un + p;
     s.F[3] = mn * ut;
     s.F[4] = (E + p) * un;
+    if constexpr (NC == 7) {
+        s.U[5] = w[1] * w[6];
+        s.F[5] = s.U[5] * un;
+    }
 }
 
-template <class R, bool FAST>
-__device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7]) {
+template <class R, bool FAST, int NC>
+__device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out[NC + 1]) {
     const R d = S - k.un;
     R chi;
     R us[5];
@@ -261,17 +290,20 @@ __device__ __forceinline__ void star_flux(const Side<R> &k, R S, R Ss, R out[7])
     for (int c = 0; c < 5; ++c) out[c] = k.F[c] + S * (us[c] - k.U[c]);
     out[5] = k.un + S * (chi - R(1));
     out[6] = k.z;
+    if constexpr (NC == 7) out[7] = k.F[5] + S * (chi * k.U[5] - k.U[5]);
 }
 
-// HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f).
-// The star state is evaluated once, for the side the contact moves away
-// from; only faces with S* == 0 exactly evaluate both sides and average.
-template <class R, bool FAST>
-__device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[6], R out[7]) {
-    Side<R> L, Rs;
+// HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f) and, with
+// NC = 7, the reactant-mass flux.  The star state is evaluated once, for the
+// side the contact moves away from; only faces with S* == 0 exactly evaluate
+// both sides and average.
+template <class R, bool FAST, int NC>
+__device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR[NC],
+                                     R out[NC + 1]) {
+    Side<R, NC> L, Rs;
     R cL, cR;
-    side_eval<R, FAST>(m, wL, L, cL);
-    side_eval<R, FAST>(m, wR, Rs, cR);
+    side_eval<R, FAST, NC>(m, wL, L, cL);
+    side_eval<R, FAST, NC>(m, wR, Rs, cR);
     const R SL = fmin(L.un - cL, Rs.un - cR);
     const R SR = fmax(L.un + cL, Rs.un + cR);
     const R dL = SL - L.un;
@@ -279,7 +311,7 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[
     const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
                             L.rho * dL - Rs.rho * dR);
     const bool useL = Ss > R(0);
-    Side<R> K;
+    Side<R, NC> K;
     K.rho = useL ? L.rho : Rs.rho;
     K.un = useL ? L.un : Rs.un;
     K.ut = useL ? L.ut : Rs.ut;
@@ -287,19 +319,19 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[
     K.z = useL ? L.z : Rs.z;
     K.E = useL ? L.E : Rs.E;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NC - 1; ++c) {
         K.U[c] = useL ? L.U[c] : Rs.U[c];
         K.F[c] = useL ? L.F[c] : Rs.F[c];
     }
-    R st[7];
-    star_flux<R, FAST>(K, useL ? SL : SR, Ss, st);
+    R st[NC + 1];
+    star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
     if (!(Ss > R(0)) && !(Ss < R(0))) {
         // contact at rest relative to the face: average of both star branches
-        R a[7], b[7];
-        star_flux<R, FAST>(L, SL, Ss, a);
-        star_flux<R, FAST>(Rs, SR, Ss, b);
+        R a[NC + 1], b[NC + 1];
+        star_flux<R, FAST, NC>(L, SL, Ss, a);
+        star_flux<R, FAST, NC>(Rs, SR, Ss, b);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) st[c] = R(0.5) * (a[c] + b[c]);
+        for (int c = 0; c < NC + 1; ++c) st[c] = R(0.5) * (a[c] + b[c]);
     }
     const bool supL = SL >= R(0);
     const bool supR = !supL && (SR <= R(0));
@@ -307,67 +339,69 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[6], const R wR[
     for (int c = 0; c < 5; ++c) out[c] = supL ? L.F[c] : (supR ? Rs.F[c] : st[c]);
     out[5] = supL ? L.un : (supR ? Rs.un : st[5]);
     out[6] = supL ? L.z : (supR ? Rs.z : st[6]);
+    if constexpr (NC == 7) out[7] = supL ? L.F[5] : (supR ? Rs.F[5] : st[7]);
 }
 
 // Update of one cell from its low- and high-face fluxes; fluxes are widened to
 // the storage type before they are differenced.
-template <class S, class R>
-__device__ __forceinline__ void update_cell(const S q[6], const R flo[7], const R fhi[7], S lam,
-                                            S qo[6]) {
+template <class S, class R, int NC>
+__device__ __forceinline__ void update_cell(const S q[NC], const R flo[NC + 1],
+                                            const R fhi[NC + 1], S lam, S qo[NC]) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) qo[c] = q[c] - lam * ((S)fhi[c] - (S)flo[c]);
     const S z = q[5];
     qo[5] = z - lam * (((S)fhi[6] - z) * (S)fhi[5] - ((S)flo[6] - z) * (S)flo[5]);
+    if constexpr (NC == 7) qo[6] = q[6] - lam * ((S)fhi[7] - (S)flo[7]);
 }
 
 // ------------------------------------------------------------------------
 // x sweep of one row of the strip.  All 256 threads call it (it holds
 // barriers); q: this thread's cell, qo: updated cell (valid for threads
 // 2..253; the halo threads return q unchanged).
-template <class S, class R, bool FAST, int LIM>
-__device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
-                                      const Mix<S> &ms, const Mix<R> &mr, R (*sWF)[kThreads],
-                                      R (*sH)[kThreads]) {
-    S w[6], r, rc2;
-    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
-    R wr[6];
+template <class S, class R, bool FAST, int LIM, int NC>
+__device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R hl,
+                                      const Mix<S> &ms, const Mix<R> &mr,
+                                      R (*sWF)[kThreads], R (*sH)[kThreads]) {
+    S w[NC], r, rc2;
+    cons_to_prim<S, FAST, NC>(ms, q, w, r, rc2);
+    R wr[NC];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < NC; ++c) {
         wr[c] = (R)w[c];
         sWF[c][t] = wr[c];
     }
     __syncthreads();
-    R wl[6], wh[6];
+    R wl[NC], wh[NC];
     if (t >= 1 && t <= kThreads - 2) {
-        R wm[6], wp[6];
+        R wm[NC], wp[NC];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
+        for (int c = 0; c < NC; ++c) {
             wm[c] = sWF[c][t - 1];
             wp[c] = sWF[c][t + 1];
         }
-        face_states<R, FAST, LIM>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
+        face_states<R, FAST, LIM, NC>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sH[c][t] = wh[c];
+        for (int c = 0; c < NC; ++c) sH[c][t] = wh[c];
     }
     __syncthreads();
-    R f[7];
+    R f[NC + 1];
     if (t >= 2 && t <= kThreads - 2) {
-        R whm[6];
+        R whm[NC];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) whm[c] = sH[c][t - 1];
-        hllc<R, FAST>(mr, whm, wl, f);
+        for (int c = 0; c < NC; ++c) whm[c] = sH[c][t - 1];
+        hllc<R, FAST, NC>(mr, whm, wl, f);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sWF[c][t] = f[c];
+        for (int c = 0; c < NC + 1; ++c) sWF[c][t] = f[c];
     }
     __syncthreads();
     if (t >= 2 && t <= kThreads - 3) {
-        R fh[7];
+        R fh[NC + 1];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) fh[c] = sWF[c][t + 1];
-        update_cell<S, R>(q, f, fh, lam, qo);
+        for (int c = 0; c < NC + 1; ++c) fh[c] = sWF[c][t + 1];
+        update_cell<S, R, NC>(q, f, fh, lam, qo);
     } else {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) qo[c] = q[c];
+        for (int c = 0; c < NC; ++c) qo[c] = q[c];
     }
     __syncthreads();
 }
@@ -375,41 +409,41 @@ __device__ __forceinline__ void x_row(const S q[6], S qo[6], int t, S lam, R hl,
 // y sweep as a rolling window down one column (registers only).  Rows are
 // pushed in order; after the 5th row the window yields the updated row two
 // behind the one pushed.  Values are in the y frame (normal momentum rho v).
-template <class S, class R, bool FAST, int LIM>
+template <class S, class R, bool FAST, int LIM, int NC>
 struct YPipe {
-    S q1[6], q2[6];      // conserved rows k-1, k-2
-    R w1[6], w2[6];      // primitives rows k-1, k-2
+    S q1[NC], q2[NC];    // conserved rows k-1, k-2
+    R w1[NC], w2[NC];    // primitives rows k-1, k-2
     R r1, c1;            // 1/rho and rho c^2 of row k-1
-    R wh2[6];            // high-face state of row k-2
-    R f2[7];             // flux through the low face of row k-2
+    R wh2[NC];           // high-face state of row k-2
+    R f2[NC + 1];        // flux through the low face of row k-2
 
     // cnt = number of rows pushed before this one (uniform across the block)
-    __device__ __forceinline__ bool push(int cnt, const S qk[6], S qo[6], S lam, R hl,
+    __device__ __forceinline__ bool push(int cnt, const S qk[NC], S qo[NC], S lam, R hl,
                                          const Mix<S> &ms, const Mix<R> &mr) {
-        S w[6], r, rc2;
-        cons_to_prim<S, FAST>(ms, qk, w, r, rc2);
-        R wk[6];
+        S w[NC], r, rc2;
+        cons_to_prim<S, FAST, NC>(ms, qk, w, r, rc2);
+        R wk[NC];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) wk[c] = (R)w[c];
+        for (int c = 0; c < NC; ++c) wk[c] = (R)w[c];
         bool out = false;
         if (cnt >= 2) {
-            R wl[6], wh[6];
-            face_states<R, FAST, LIM>(w2, w1, wk, r1, c1, hl, wl, wh);
+            R wl[NC], wh[NC];
+            face_states<R, FAST, LIM, NC>(w2, w1, wk, r1, c1, hl, wl, wh);
             if (cnt >= 3) {
-                R f[7];
-                hllc<R, FAST>(mr, wh2, wl, f);
+                R f[NC + 1];
+                hllc<R, FAST, NC>(mr, wh2, wl, f);
                 if (cnt >= 4) {
-                    update_cell<S, R>(q2, f2, f, lam, qo);
+                    update_cell<S, R, NC>(q2, f2, f, lam, qo);
                     out = true;
                 }
 #pragma unroll
-                for (int c = 0; c < 7; ++c) f2[c] = f[c];
+                for (int c = 0; c < NC + 1; ++c) f2[c] = f[c];
             }
 #pragma unroll
-            for (int c = 0; c < 6; ++c) wh2[c] = wh[c];
+            for (int c = 0; c < NC; ++c) wh2[c] = wh[c];
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
+        for (int c = 0; c < NC; ++c) {
             q2[c] = q1[c]; q1[c] = qk[c];
             w2[c] = w1[c]; w1[c] = wk[c];
         }
@@ -419,17 +453,45 @@ struct YPipe {
     }
 };
 
-template <class S> __device__ __forceinline__ void to_yframe(const S a[6], S b[6]) {
+template <class S, int NC> __device__ __forceinline__ void to_yframe(const S a[NC], S b[NC]) {
     b[0] = a[0]; b[1] = a[1]; b[2] = a[3]; b[3] = a[2]; b[4] = a[4]; b[5] = a[5];
+    if constexpr (NC == 7) b[6] = a[6];
 }
 
-// Pointwise stage and CFL contribution of one updated cell (U order).
+// Pointwise reaction stage over a time h (Strang split, Sec. 3) of one cell of
+// a reactive liquid: Arrhenius rate K = -lambda C exp(-Ta / T2) (Eq. (6)) at
+// the liquid temperature T2 = (p - p_ref(rho2)) / (rho2 Gamma_0 c_v) of
+// Eq. (5) (T_ref = 0), held fixed over the stage, so lambda decays exactly by
+// exp(-C exp(-Ta / T2) h); the reacted liquid mass releases Q per unit mass
+// into rho E (source of Eq. (1)).  Cells without reactant or with T2 <= 0
+// are left as they are.
 template <class S, bool FAST>
-__device__ __forceinline__ void epilogue(S q[6], const Mix<S> &ms, S zlo, S zhi, S idx, S idy,
-                                         S &smax, int &bad) {
+__device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S h) {
+    if (!(q[6] > S(0))) return;
+    S w[7], r, rc2;
+    cons_to_prim<S, FAST, 7>(m, q, w, r, rc2);
+    const S rho2 = Ar<S, FAST>::div(q[1], S(1) - q[5]);
+    const S v = Ar<S, FAST>::div(m.rho0, rho2);
+    S vc, vd;
+    Ar<S, FAST>::pw(v, m.C, m.D, vc, vd);
+    const S pref = m.A * vc - m.B * vd;
+    const S T = Ar<S, FAST>::div(w[4] - pref, (rho2 * x.G0) * x.cv);
+    if (!(T > S(0))) return;
+    const S k = x.C * Ar<S, FAST>::ex(-Ar<S, FAST>::div(x.Ta, T));
+    const S lam_new = w[6] * Ar<S, FAST>::ex(-k * h);
+    q[4] = q[4] + x.Q * (q[6] - q[1] * lam_new);
+    q[6] = q[1] * lam_new;
+}
+
+// Pointwise stage and CFL contribution of one updated cell (U order): the z1
+// clamp, the second half of the reaction (NC = 7), then the signal speed.
+template <class S, bool FAST, int NC>
+__device__ __forceinline__ void epilogue(S q[NC], const Mix<S> &ms, const Rx<S> &rx, S hdt,
+                                         S zlo, S zhi, S idx, S idy, S &smax, int &bad) {
     q[5] = fmin(fmax(q[5], zlo), zhi);
-    S w[6], r, rc2;
-    cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+    if constexpr (NC == 7) react<S, FAST>(q, ms, rx, hdt);
+    S w[NC], r, rc2;
+    cons_to_prim<S, FAST, NC>(ms, q, w, r, rc2);
     const S c = Ar<S, FAST>::sqrt_(rc2 * r);
     const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
     if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
@@ -469,17 +531,27 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // One tile of the state update: strip bx (252 written columns) and row
 // segment by of the solve described by d.  MODE: kXY / kYX (fused step), kX /
 // kY (one sweep).  FINAL: this pass produces the end-of-step state (pointwise
-// stage + CFL contribution).  All threads of the workgroup call it.
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+// stage + CFL contribution).  A pass that starts a step (fused, or the first
+// of two sweeps) applies the first half of the reaction stage (NC = 7) to
+// every value it loads, halo cells included.  All threads of the workgroup
+// call it.
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
                                          R (*sWF)[kThreads], R (*sH)[kThreads]) {
     Control *ctl = d.ctl;
     const S lamx = (S)ctl->lam_x, lamy = (S)ctl->lam_y;
     const R hlx = (R)ctl->hl_x, hly = (R)ctl->hl_y;
     const int slot = (int)((ctl->step_exec + 1) & 1);
+    constexpr bool kStarts = (MODE == kXY) || (MODE == kYX) || !FINAL;
 
     const Mix<S> ms = mix_of<S>(d);
     const Mix<R> mr = mix_of<R>(d);
+    Rx<S> rx{};
+    S hdt = S(0);
+    if constexpr (NC == 7) {
+        rx = rx_of<S>(d);
+        hdt = (S)(0.5 * ctl->dt);
+    }
     const S *src = (const S *)d.buf[src_idx];
     S *dst = (S *)d.buf[src_idx ^ 1];
     const long long plane = d.plane;
@@ -495,59 +567,64 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     S smax = S(0);
     int bad = 0;
 
-    auto load = [&](int k, S q[6]) {
+    auto load = [&](int k, S q[NC]) {
         const int gk = map_idx(k, d.ny, d.bc_ylo, d.bc_yhi);
         const long long o = (long long)gk * d.pitch + gcol;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) q[c] = src[c * plane + o];
+        for (int c = 0; c < NC; ++c) q[c] = src[c * plane + o];
     };
-    auto store = [&](int k, S q[6]) {
-        if (FINAL) epilogue<S, FAST>(q, ms, zlo, zhi, idx, idy, smax, bad);
+    auto start = [&](S q[NC]) {
+        if constexpr (NC == 7 && kStarts) react<S, FAST>(q, ms, rx, hdt);
+    };
+    auto store = [&](int k, S q[NC]) {
+        if (FINAL) epilogue<S, FAST, NC>(q, ms, rx, hdt, zlo, zhi, idx, idy, smax, bad);
         const long long o = (long long)k * d.pitch + col;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) dst[c * plane + o] = q[c];
+        for (int c = 0; c < NC; ++c) dst[c * plane + o] = q[c];
     };
 
     if (MODE == kX) {
-        S qn[6];
+        S qn[NC];
         load(y0, qn);
         for (int k = y0; k < y1; ++k) {
-            S q[6], qo[6];
+            S q[NC], qo[NC];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            for (int c = 0; c < NC; ++c) q[c] = qn[c];
             if (k + 1 < y1) load(k + 1, qn);
-            x_row<S, R, FAST, LIM>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            start(q);
+            x_row<S, R, FAST, LIM, NC>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
             if (out_col) store(k, qo);
         }
     } else {
-        YPipe<S, R, FAST, LIM> yp;
+        YPipe<S, R, FAST, LIM, NC> yp;
         const int k0 = y0 - kHalo, k1 = y1 + kHalo;
-        S qn[6];
+        S qn[NC];
         load(k0, qn);
         for (int k = k0; k < k1; ++k) {
             const int cnt = k - k0;
-            S q[6];
+            S q[NC];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) q[c] = qn[c];
+            for (int c = 0; c < NC; ++c) q[c] = qn[c];
             if (k + 1 < k1) load(k + 1, qn);
+            start(q);
             if (MODE == kXY) {
-                S qs[6], qy[6], qo[6], qu[6];
-                x_row<S, R, FAST, LIM>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
-                to_yframe<S>(qs, qy);
+                S qs[NC], qy[NC], qo[NC], qu[NC];
+                x_row<S, R, FAST, LIM, NC>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                to_yframe<S, NC>(qs, qy);
                 if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
-                    to_yframe<S>(qo, qu);
+                    to_yframe<S, NC>(qo, qu);
                     if (out_col) store(k - kHalo, qu);
                 }
             } else {
-                S qy[6], qo[6], qu[6];
-                to_yframe<S>(q, qy);
+                S qy[NC], qo[NC], qu[NC];
+                to_yframe<S, NC>(q, qy);
                 const bool got = yp.push(cnt, qy, qo, lamy, hly, ms, mr);
-                to_yframe<S>(qo, qu);
+                to_yframe<S, NC>(qo, qu);
                 if (MODE == kY) {
                     if (got && out_col) store(k - kHalo, qu);
                 } else if (got) {  // kYX: x sweep of the row just finished in y
-                    S qx[6];
-                    x_row<S, R, FAST, LIM>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    S qx[NC];
+                    x_row<S, R, FAST, LIM, NC>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
                     if (out_col) store(k - kHalo, qx);
                 }
             }
@@ -557,17 +634,18 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
 }
 
 // State update of one solve: grid (strips, segments).
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL>
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC = 6>
 __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
-    __shared__ R sWF[7][kThreads];
-    __shared__ R sH[6][kThreads];
+    __shared__ R sWF[NC + 1][kThreads];
+    __shared__ R sH[NC][kThreads];
     if (d.ctl->skip) return;
-    run_tile<S, R, FAST, LIM, MODE, FINAL>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
+    run_tile<S, R, FAST, LIM, MODE, FINAL, NC>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
 }
 
 // Fused state update of many solves in one launch: workgroup b takes tile
 // tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
-// (x-y order and source copy), read from its control block.
+// (x-y order and source copy), read from its control block.  Inert solves
+// only (NC = 6).
 template <class S, class R, bool FAST, int LIM>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
                                                                 const int4 *tiles) {
@@ -577,8 +655,41 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *desc
     const Desc d = descs[tl.x];
     if (d.ctl->skip) return;
     const int par = (int)(d.ctl->step_exec & 1);
-    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true>(d, tl.y, tl.z, 0, sWF, sH);
-    else run_tile<S, R, FAST, LIM, kYX, true>(d, tl.y, tl.z, 1, sWF, sH);
+    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6>(d, tl.y, tl.z, 0, sWF, sH);
+    else run_tile<S, R, FAST, LIM, kYX, true, 6>(d, tl.y, tl.z, 1, sWF, sH);
+}
+
+// Host-side launch of the step kernel variant for one sweep mode (kXY, kYX,
+// or a single sweep kX / kY that does or does not end the step).
+template <class S, class R, bool FAST, int LIM, int NC>
+void launch_step_variants(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
+    const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
+    switch (mode) {
+        case kXY:
+            hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kXY, true, NC>), grid, block, 0, st,
+                               d, src);
+            break;
+        case kYX:
+            hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kYX, true, NC>), grid, block, 0, st,
+                               d, src);
+            break;
+        case kX:
+            if (final_pass)
+                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, true, NC>), grid, block, 0,
+                                   st, d, src);
+            else
+                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, false, NC>), grid, block, 0,
+                                   st, d, src);
+            break;
+        default:
+            if (final_pass)
+                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, true, NC>), grid, block, 0,
+                                   st, d, src);
+            else
+                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, false, NC>), grid, block, 0,
+                                   st, d, src);
+            break;
+    }
 }
 
 }  // namespace meso

@@ -39,7 +39,7 @@ struct alignas(256) Control {
 
 // Everything a step kernel needs to know about one solve.
 struct Desc {
-    void *buf[2];            // two state copies, 6 planes each
+    void *buf[2];            // two state copies, nc planes each
     Control *ctl;
     int nx, ny;
     int pitch;               // elements per row
@@ -52,10 +52,13 @@ struct Desc {
     double zlo, zhi;         // eps, 1 - eps of the pointwise stage
     double g1, g2, h1, h2;   // mixture constants 1/Gamma_k, phi_k of stiffened gases
     int eos2;                // liquid EoS: 0 stiffened gas, 1 Cochran-Chan
-    int pad_;
+    int nc;                  // conserved planes: 6, or 7 with the reactant mass
     // Cochran-Chan liquid: A, B, C, D, rho0, 1/Gamma0, -A/(rho0(1-C)), B/(rho0(1-D)),
     // A*C, B*D
     double cA, cB, cC, cD, crho0, ciG, ckA, ckB, cAC, cBD;
+    // reactive liquid: Gamma0 and c_v (temperature, Eq. (5)); Arrhenius C, Ta
+    // and heat of reaction Q (Eq. (6), Table 3)
+    double cG0, rxcv, rxC, rxTa, rxQ;
 };
 
 // Host helpers shared by the solver and the server (meso_api.hip).
@@ -64,9 +67,11 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int pitch_of(int nx) { return (int)round_up((size_t)nx, 64); }
 bool valid_grid(const mf_grid *g);
 bool valid_materials(const mf_material *mat);
+// conserved planes of a solve with these materials: 7 if the liquid reacts
+int planes_of(const mf_material *mat);
 bool valid_scheme(const mf_options *opt);
-// bytes of one pitched state copy (6 planes), 256-byte rounded
-size_t state_bytes(const mf_grid *g, int prec);
+// bytes of one pitched state copy (nc planes), 256-byte rounded
+size_t state_bytes(const mf_grid *g, int prec, int nc);
 int choose_seg_h(int nstrips, int ny);
 // Fill a descriptor for a solve whose workspace (control block + two state
 // copies) starts at base.
@@ -87,7 +92,7 @@ hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pas
                        hipStream_t st);
 hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double *out,
                              hipStream_t st);
-// Diagnostics: out = 9 * nx doubles (pbar, rhobar, ubar, 6 column sums);
+// Diagnostics: out = (3 + nc) * nx doubles (pbar, rhobar, ubar, nc column sums);
 // integrals from those column sums; a mass-weighted log-binned histogram.
 hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStream_t st);
 hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipStream_t st);
@@ -103,5 +108,11 @@ hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int fina
                             hipStream_t st);
 hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
                                     int lim, hipStream_t st);
+// Reactive solves (seven components): FP64 (meso_kernels_react.hip) and the
+// FP32-bulk / FP32 modes (meso_kernels_react_fast.hip).
+hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+                             hipStream_t st);
+hipError_t launch_step_react_fast(const Desc &d, int prec, int lim, int mode, int final_pass,
+                                  int src, hipStream_t st);
 
 }  // namespace meso

@@ -127,6 +127,7 @@ __global__ void prim_to_cons_kernel(Desc d, int dst_idx, const double *prim) {
         dst[3 * d.plane + o] = (S)(rho * v);
         dst[4 * d.plane + o] = (S)E;
         dst[5 * d.plane + o] = (S)z;
+        if (d.nc == 7) dst[6 * d.plane + o] = (S)(a2 * prim[6 * N + k]);   // z2 rho2 lambda
     }
 }
 
@@ -138,8 +139,7 @@ __global__ void cons_from_f64_kernel(Desc d, int dst_idx, const double *cons) {
          k += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
         const long long o = (long long)j * d.pitch + i;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) dst[c * d.plane + o] = (S)cons[c * N + k];
+        for (int c = 0; c < d.nc; ++c) dst[c * d.plane + o] = (S)cons[c * N + k];
     }
 }
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, i
         S q[6], w[6], r, rc2;
 #pragma unroll
         for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
-        cons_to_prim<S, FAST>(ms, q, w, r, rc2);
+        cons_to_prim<S, FAST, 6>(ms, q, w, r, rc2);
         const S c = Ar<S, FAST>::sqrt_(rc2 * r);
         const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
         if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
@@ -169,25 +169,61 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, i
     block_cfl_commit((double)smax, bad, d.ctl, slot);
 }
 
-// One field of the state as dense FP64 (conserved planes are widened,
-// derived fields use the closure in the storage type).
+// Liquid temperature of Eq. (5) (T_ref = 0, constant Gamma_0 and c_v) of a
+// cell of a reactive Cochran-Chan liquid, evaluated in FP64.
+__device__ __forceinline__ double liquid_temperature(const Mix<double> &m, const Rx<double> &x,
+                                                     const double q[7]) {
+    double w[7], r, rc2;
+    cons_to_prim<double, false, 7>(m, q, w, r, rc2);
+    const double rho2 = q[1] / (1.0 - q[5]);
+    const double v = m.rho0 / rho2;
+    double vc, vd;
+    Ar<double, false>::pw(v, m.C, m.D, vc, vd);
+    const double pref = m.A * vc - m.B * vd;
+    return (w[4] - pref) / ((rho2 * x.G0) * x.cv);
+}
+
+// Volumetric heat-release rate -z2 rho2 K Q of the reactive liquid (Sec. 4.5)
+// in GW/m^3; 0 without reactant or at T2 <= 0.
+__device__ __forceinline__ double heat_release(const Mix<double> &m, const Rx<double> &x,
+                                               const double q[7]) {
+    if (!(q[6] > 0.0)) return 0.0;
+    const double T = liquid_temperature(m, x, q);
+    if (!(T > 0.0)) return 0.0;
+    return ((q[6] * x.C) * exp(-x.Ta / T) * x.Q) * 1.0e-9;
+}
+
+// One field of the state as dense FP64 (conserved planes are widened, derived
+// fields 6-10 use the closure in the storage type, the reaction fields 12-14
+// the FP64 closure of the widened state).
 template <class S>
 __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
     const long long N = (long long)d.nx * d.ny;
     const S *src = (const S *)d.buf[src_idx];
     const Mix<S> ms = mix_of<S>(d);
+    const Mix<double> md = mix_of<double>(d);
+    const Rx<double> rx = rx_of<double>(d);
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
          k += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
         const long long o = (long long)j * d.pitch + i;
-        if (field < 6) {
-            out[k] = (double)src[field * d.plane + o];
+        if (field < 6 || field == MF_Z2RHO2LAM) {
+            out[k] = (double)src[(field < 6 ? field : 6) * d.plane + o];
+            continue;
+        }
+        if (field >= MF_LAMBDA) {
+            double q[7];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) q[c] = (double)src[c * d.plane + o];
+            if (field == MF_LAMBDA) out[k] = q[6] / q[1];
+            else if (field == MF_T2) out[k] = liquid_temperature(md, rx, q);
+            else out[k] = heat_release(md, rx, q);
             continue;
         }
         S q[6], w[6], r, rc2;
 #pragma unroll
         for (int c = 0; c < 6; ++c) q[c] = src[c * d.plane + o];
-        cons_to_prim<S, false>(ms, q, w, r, rc2);
+        cons_to_prim<S, false, 6>(ms, q, w, r, rc2);
         double v;
         switch (field) {
             case 6: v = (double)(q[0] + q[1]); break;
@@ -214,31 +250,31 @@ __global__ void column_kernel(Desc d, int src_idx, double *out) {
     if (i >= d.nx) return;
     const S *src = (const S *)d.buf[src_idx];
     const Mix<double> m = mix_of<double>(d);
-    double sp = 0.0, sr = 0.0, sm = 0.0, sc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int nc = d.nc;
+    double sp = 0.0, sr = 0.0, sm = 0.0, sc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < d.ny; ++j) {
         const long long o = (long long)j * d.pitch + i;
-        double q[6], w[6], r, rc2;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) q[c] = (double)src[c * d.plane + o];
-        cons_to_prim<double, false>(m, q, w, r, rc2);
+        double q[7], w[6], r, rc2;
+        q[6] = 0.0;
+        for (int c = 0; c < nc; ++c) q[c] = (double)src[c * d.plane + o];
+        cons_to_prim<double, false, 6>(m, q, w, r, rc2);
         sp = sp + w[4];
         sr = sr + (q[0] + q[1]);
         sm = sm + q[2];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sc[c] = sc[c] + q[c];
+        for (int c = 0; c < 7; ++c) sc[c] = sc[c] + q[c];
     }
     const long long n = d.nx;
     out[i] = sp / (double)d.ny;
     out[n + i] = sr / (double)d.ny;
     out[2 * n + i] = sm / sr;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) out[(3 + c) * n + i] = sc[c];
+    for (int c = 0; c < nc; ++c) out[(3 + c) * n + i] = sc[c];
 }
 
 // Domain integrals from the column sums (one thread, increasing i).
-__global__ void integrals_kernel(int nx, double area, const double *cols, double *out) {
+__global__ void integrals_kernel(int nx, int nc, double area, const double *cols, double *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < nc; ++c) {
         double tot = 0.0;
         const double *s = cols + (long long)(3 + c) * nx;
         for (int i = 0; i < nx; ++i) tot = tot + s[i];
@@ -249,7 +285,8 @@ __global__ void integrals_kernel(int nx, double area, const double *cols, double
 constexpr int kMaxBins = 1024;
 
 // Mass-weighted histogram over log-spaced bins: bin a (edges[a] <= v <
-// edges[a+1], v = pressure or density) collects z2 rho2 * area.  Per-workgroup
+// edges[a+1], v = pressure, density or the heat-release rate of a reactive
+// liquid) collects z2 rho2 * area.  Per-workgroup
 // LDS histograms, then one global atomic add per non-empty bin.
 template <class S>
 __global__ __launch_bounds__(kThreads) void histo_kernel(Desc d, int src_idx, int field,
@@ -262,16 +299,24 @@ __global__ __launch_bounds__(kThreads) void histo_kernel(Desc d, int src_idx, in
     __syncthreads();
     const S *src = (const S *)d.buf[src_idx];
     const Mix<double> m = mix_of<double>(d);
+    const Rx<double> rx = rx_of<double>(d);
     const long long N = (long long)d.nx * d.ny;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
          k += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
         const long long o = (long long)j * d.pitch + i;
-        double q[6], w[6], r, rc2;
+        double q[7], v;
+        if (field == MF_QDOT) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) q[c] = (double)src[c * d.plane + o];
-        cons_to_prim<double, false>(m, q, w, r, rc2);
-        const double v = (field == 6) ? (q[0] + q[1]) : w[4];
+            for (int c = 0; c < 7; ++c) q[c] = (double)src[c * d.plane + o];
+            v = heat_release(m, rx, q);
+        } else {
+            double w[6], r, rc2;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) q[c] = (double)src[c * d.plane + o];
+            cons_to_prim<double, false, 6>(m, q, w, r, rc2);
+            v = (field == 6) ? (q[0] + q[1]) : w[4];
+        }
         if (!(v >= e[0]) || !(v < e[nbins])) continue;
         int a = 0, z = nbins;
         while (z - a > 1) {
@@ -351,28 +396,12 @@ hipError_t launch_dt(const Desc &d, double cfl, double dx, double dy, double dt_
     return hipGetLastError();
 }
 
-template <class S, class R, bool FAST, int LIM>
-static void launch_step_t(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
-    const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
-    switch (mode) {
-        case kXY: hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kXY, true>), grid, block, 0, st, d, src); break;
-        case kYX: hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kYX, true>), grid, block, 0, st, d, src); break;
-        case kX:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, false>), grid, block, 0, st, d, src);
-            break;
-        default:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, false>), grid, block, 0, st, d, src);
-            break;
-    }
-}
-
 hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                        hipStream_t st) {
+    if (d.nc == 7) return launch_step_react(d, prec, lim, mode, final_pass, src, st);
     if (prec != kP64) return launch_step_fast(d, prec, lim, mode, final_pass, src, st);
-    if (lim == 1) launch_step_t<double, double, false, 1>(d, mode, final_pass, src, st);
-    else launch_step_t<double, double, false, 0>(d, mode, final_pass, src, st);
+    if (lim == 1) launch_step_variants<double, double, false, 1, 6>(d, mode, final_pass, src, st);
+    else launch_step_variants<double, double, false, 0, 6>(d, mode, final_pass, src, st);
     return hipGetLastError();
 }
 
@@ -418,7 +447,8 @@ hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStre
 }
 
 hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(integrals_kernel, dim3(1), dim3(64), 0, st, d.nx, d.dx * d.dy, cols, out);
+    hipLaunchKernelGGL(integrals_kernel, dim3(1), dim3(64), 0, st, d.nx, d.nc, d.dx * d.dy, cols,
+                       out);
     return hipGetLastError();
 }
 

@@ -6,31 +6,14 @@
 
 namespace meso {
 
-template <class S, class R, int LIM>
-static void launch_fast_t(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
-    const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
-    switch (mode) {
-        case kXY: hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kXY, true>), grid, block, 0, st, d, src); break;
-        case kYX: hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kYX, true>), grid, block, 0, st, d, src); break;
-        case kX:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kX, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kX, false>), grid, block, 0, st, d, src);
-            break;
-        default:
-            if (final_pass) hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kY, true>), grid, block, 0, st, d, src);
-            else hipLaunchKernelGGL((step_kernel<S, R, true, LIM, kY, false>), grid, block, 0, st, d, src);
-            break;
-    }
-}
-
 hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                             hipStream_t st) {
     if (prec == kPMix) {
-        if (lim == 1) launch_fast_t<double, float, 1>(d, mode, final_pass, src, st);
-        else launch_fast_t<double, float, 0>(d, mode, final_pass, src, st);
+        if (lim == 1) launch_step_variants<double, float, true, 1, 6>(d, mode, final_pass, src, st);
+        else launch_step_variants<double, float, true, 0, 6>(d, mode, final_pass, src, st);
     } else {
-        if (lim == 1) launch_fast_t<float, float, 1>(d, mode, final_pass, src, st);
-        else launch_fast_t<float, float, 0>(d, mode, final_pass, src, st);
+        if (lim == 1) launch_step_variants<float, float, true, 1, 6>(d, mode, final_pass, src, st);
+        else launch_step_variants<float, float, true, 0, 6>(d, mode, final_pass, src, st);
     }
     return hipGetLastError();
 }

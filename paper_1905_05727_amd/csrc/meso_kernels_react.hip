@@ -1,0 +1,18 @@
+// meso_kernels_react.hip -- step kernels of a reactive liquid (seven conserved
+// components: the reactant mass z2 rho2 lambda is advected with the flow and
+// reacts in the pointwise stage), FP64 mode.  Built without floating-point
+// contraction, like the inert FP64 kernels.
+
+#include "meso_device.h"
+
+namespace meso {
+
+hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+                             hipStream_t st) {
+    if (prec != kP64) return launch_step_react_fast(d, prec, lim, mode, final_pass, src, st);
+    if (lim == 1) launch_step_variants<double, double, false, 1, 7>(d, mode, final_pass, src, st);
+    else launch_step_variants<double, double, false, 0, 7>(d, mode, final_pass, src, st);
+    return hipGetLastError();
+}
+
+}  // namespace meso

@@ -183,7 +183,7 @@ int32_t ring_pinned(std::vector<Pinned> &ring, size_t &next, size_t bytes, Pinne
 }
 
 size_t request_bytes(const mf_grid *g, int prec) {
-    return meso::kAlign + 2 * meso::state_bytes(g, prec) + readback_bytes(g);
+    return meso::kAlign + 2 * meso::state_bytes(g, prec, 6) + readback_bytes(g);
 }
 
 // Upload and convert a request's initial state into a free slot.
@@ -317,7 +317,7 @@ int32_t start_drain(mf_server *s, Slot &sl) {
     }
     sl.pin = pin;
     sl.draining = true;
-    double *dense = (double *)(s->arena + sl.off + meso::kAlign + 2 * meso::state_bytes(&r.grid, s->cfg.precision));
+    double *dense = (double *)(s->arena + sl.off + meso::kAlign + 2 * meso::state_bytes(&r.grid, s->cfg.precision, 6));
     const int src = (int)(sl.nsteps & 1);
     hipError_t e = hipSuccess;
     for (int f = 0; f < 6 && e == hipSuccess; ++f)
@@ -430,7 +430,8 @@ int32_t mf_server_submit(mf_server *s, const mf_grid *grid, const mf_material ma
                          const mf_options *opt, const double *prim, int64_t nsteps,
                          uint64_t *ticket) {
     if (!s || !prim || !ticket || nsteps < 1) return MF_E_INVALID_ARG;
-    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt))
+    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt) ||
+        mat[1].reactive != 0)
         return MF_E_INVALID_ARG;
     if (opt->precision != s->cfg.precision || opt->limiter != s->cfg.limiter)
         return MF_E_INVALID_ARG;

@@ -22,7 +22,9 @@ PRECISION = {"fp64": 0, "fp32_fp64acc": 1, "mixed": 1, "fp32": 2}
 LIMITER = {"vanleer": 0, "minmod": 1}
 BC = {"transmissive": 0, "periodic": 1}
 FIELDS = {"z1rho1": 0, "z2rho2": 1, "rhou": 2, "rhov": 3, "rhoE": 4, "z1": 5,
-          "rho": 6, "u": 7, "v": 8, "p": 9, "c": 10}
+          "rho": 6, "u": 7, "v": 8, "p": 9, "c": 10,
+          # reactive solvers only
+          "z2rho2lam": 11, "lam": 12, "T2": 13, "qdot": 14}
 
 # every symbol the header declares
 EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conserved",
@@ -48,9 +50,11 @@ class Grid(C.Structure):
 
 
 class Material(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("gamma", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("reactive", C.c_int32), ("gamma", C.c_double),
                 ("p_inf", C.c_double), ("gamma0", C.c_double), ("A", C.c_double),
-                ("B", C.c_double), ("C", C.c_double), ("D", C.c_double), ("rho0", C.c_double)]
+                ("B", C.c_double), ("C", C.c_double), ("D", C.c_double), ("rho0", C.c_double),
+                ("cv", C.c_double), ("arr_C", C.c_double), ("arr_Ta", C.c_double),
+                ("heat_Q", C.c_double)]
 
 
 EOS_STIFFENED, EOS_COCHRAN_CHAN = 0, 1
@@ -58,19 +62,27 @@ EOS_STIFFENED, EOS_COCHRAN_CHAN = 0, 1
 
 def stiffened(gamma: float, p_inf: float = 0.0) -> Material:
     """Stiffened gas p = (gamma - 1) rho e - gamma p_inf (air: p_inf = 0)."""
-    return Material(EOS_STIFFENED, 0, float(gamma), float(p_inf), 0, 0, 0, 0, 0, 0)
+    return Material(EOS_STIFFENED, 0, float(gamma), float(p_inf), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0)
 
 
-def cochran_chan(gamma0, A, B, C_, D, rho0) -> Material:
-    """Cochran-Chan liquid (Eqs. (2)-(4)); constants as in Table 1."""
-    return Material(EOS_COCHRAN_CHAN, 0, 0.0, 0.0, float(gamma0), float(A), float(B),
-                    float(C_), float(D), float(rho0))
+def cochran_chan(gamma0, A, B, C_, D, rho0, rx=None) -> Material:
+    """Cochran-Chan liquid (Eqs. (2)-(4)); constants as in Table 1.  rx =
+    (C [1/s], Ta [K], Q [J/kg], c_v [J/(kg K)]) makes it reactive (Eq. (6),
+    Table 3; temperature of Eq. (5))."""
+    m = Material(EOS_COCHRAN_CHAN, 0, 0.0, 0.0, float(gamma0), float(A), float(B),
+                 float(C_), float(D), float(rho0), 0, 0, 0, 0)
+    if rx is not None:
+        m.reactive = 1
+        m.arr_C, m.arr_Ta, m.heat_Q, m.cv = (float(v) for v in rx)
+    return m
 
 
 def materials_of(sc) -> "C.Array":
     """(gas, liquid) materials of a scenario."""
-    liquid = cochran_chan(*sc.cc) if getattr(sc, "eos2", 0) == 1 else stiffened(sc.gamma2,
-                                                                                sc.pinf2)
+    if getattr(sc, "eos2", 0) == 1:
+        liquid = cochran_chan(*sc.cc, rx=sc.rx if getattr(sc, "reactive", False) else None)
+    else:
+        liquid = stiffened(sc.gamma2, sc.pinf2)
     return (Material * 2)(stiffened(sc.gamma1, sc.pinf1), liquid)
 
 
@@ -106,7 +118,7 @@ def load_library():
     I64 = C.POINTER(C.c_int64)
     I32 = C.POINTER(C.c_int32)
     sig = {
-        "mf_workspace_bytes": (C.c_size_t, [C.POINTER(Grid), C.c_int32]),
+        "mf_workspace_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Material), C.c_int32]),
         "mf_create": (C.c_int32, [C.POINTER(Grid), C.POINTER(Material), C.POINTER(Options),
                                   P, C.c_size_t, P, C.POINTER(P)]),
         "mf_set_primitive": (C.c_int32, [P, D]),
@@ -163,9 +175,10 @@ def make_grid(nx, ny, dx, dy, bc=("transmissive",) * 4) -> Grid:
     return Grid(int(nx), int(ny), float(dx), float(dy), *b)
 
 
-def workspace_bytes(nx, ny, dx=1.0, dy=1.0, precision="fp64", bc=("transmissive",) * 4) -> int:
+def workspace_bytes(nx, ny, dx=1.0, dy=1.0, precision="fp64", bc=("transmissive",) * 4,
+                    mats=None) -> int:
     g = make_grid(nx, ny, dx, dy, bc)
-    return int(load_library().mf_workspace_bytes(C.byref(g), PRECISION[precision]))
+    return int(load_library().mf_workspace_bytes(C.byref(g), mats, PRECISION[precision]))
 
 
 class Solver:
@@ -184,9 +197,10 @@ class Solver:
         self._grid = make_grid(nx, ny, dx, dy, bc)
         mats = (Material * 2)(stiffened(gamma1, pinf1),
                               liquid if liquid is not None else stiffened(gamma2, pinf2))
+        self.nplanes = 7 if mats[1].reactive else 6
         opt = Options(float(cfl), float(z_floor), LIMITER[limiter], PRECISION[precision],
                       1 if fused else 0, 0)
-        nbytes = int(lib.mf_workspace_bytes(C.byref(self._grid), PRECISION[precision]))
+        nbytes = int(lib.mf_workspace_bytes(C.byref(self._grid), mats, PRECISION[precision]))
         if nbytes == 0:
             raise MesoError("mf_workspace_bytes", -1)
         self._ws = None
@@ -213,12 +227,12 @@ class Solver:
 
     def set_primitive(self, prim: np.ndarray) -> None:
         prim = np.ascontiguousarray(prim, dtype=np.float64)
-        assert prim.size == 6 * self.nx * self.ny
+        assert prim.size == self.nplanes * self.nx * self.ny
         _chk("mf_set_primitive", self._lib.mf_set_primitive(self._h, _dptr(prim)))
 
     def set_conserved(self, U: np.ndarray) -> None:
         U = np.ascontiguousarray(U, dtype=np.float64)
-        assert U.size == 6 * self.nx * self.ny
+        assert U.size == self.nplanes * self.nx * self.ny
         _chk("mf_set_conserved", self._lib.mf_set_conserved(self._h, _dptr(U)))
 
     def set_time(self, t: float, step: int) -> None:
@@ -248,7 +262,7 @@ class Solver:
         return out
 
     def read_conserved(self) -> np.ndarray:
-        out = np.empty((6, self.ny, self.nx), dtype=np.float64)
+        out = np.empty((self.nplanes, self.ny, self.nx), dtype=np.float64)
         _chk("mf_read_conserved", self._lib.mf_read_conserved(self._h, _dptr(out), out.size))
         return out
 
@@ -268,8 +282,10 @@ class Solver:
         return p, r, u
 
     def integrals(self) -> np.ndarray:
-        out = np.empty(6)
-        _chk("mf_integrals", self._lib.mf_integrals(self._h, _dptr(out), 6))
+        """Domain integrals of the conserved components and z1 (and the
+        remaining reactant mass M_2,r of Eq. (10) for a reactive solver)."""
+        out = np.empty(self.nplanes)
+        _chk("mf_integrals", self._lib.mf_integrals(self._h, _dptr(out), self.nplanes))
         return out
 
     def log_histogram(self, field, lo: float, dn: float, nbins: int, m_ref: float):

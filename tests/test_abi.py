@@ -34,17 +34,36 @@ def test_status_strings_and_version():
     assert lib.mf_version().startswith(b"meso")
 
 
+NM = (1.19, 0.819e9, 1.51e9, 4.53, 1.42, 1134.0)
+RX = (2.6e9, 11350.0, 4.46e6, 1714.0)
+
+
+def reactive_pair():
+    return (meso.Material * 2)(meso.stiffened(1.4, 0.0), meso.cochran_chan(*NM, rx=RX))
+
+
 def test_workspace_bytes():
     lib = meso.load_library()
     for nx, ny in ((1, 1), (1000, 1), (1024, 512), (8192, 8192)):
         pitch = (nx + 63) // 64 * 64
         for prec, es in (("fp64", 8), ("fp32_fp64acc", 8), ("fp32", 4)):
-            state = (6 * pitch * ny * es + 255) // 256 * 256
-            assert meso.workspace_bytes(nx, ny, precision=prec) == 256 + 2 * state
+            for mats, nc in ((None, 6), (reactive_pair(), 7)):
+                state = (nc * pitch * ny * es + 255) // 256 * 256
+                assert meso.workspace_bytes(nx, ny, precision=prec, mats=mats) == 256 + 2 * state
     g = meso.make_grid(0, 5, 1.0, 1.0)
-    assert lib.mf_workspace_bytes(C.byref(g), 0) == 0
+    assert lib.mf_workspace_bytes(C.byref(g), None, 0) == 0
     g = meso.make_grid(5, 5, 1.0, 1.0)
-    assert lib.mf_workspace_bytes(C.byref(g), 7) == 0
+    assert lib.mf_workspace_bytes(C.byref(g), None, 7) == 0
+    bad = reactive_pair()
+    bad[1].cv = 0.0
+    assert lib.mf_workspace_bytes(C.byref(g), bad, 0) == 0
+
+
+def _reactive(**kw):
+    m = meso.cochran_chan(*NM, rx=RX)
+    for k, v in kw.items():
+        setattr(m, k, v)
+    return m
 
 
 def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
@@ -71,6 +90,16 @@ def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
                                   meso.cochran_chan(1.19, 0.819e9, 1.51e9, 1.0, 1.42, 1134.0))),
     dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0),
                                   meso.cochran_chan(1.19, 0.819e9, 1.51e9, 4.53, 1.42, -1.0))),
+    # reaction: liquid only, Cochran-Chan only, positive c_v and rate constant
+    dict(mats=(meso.Material * 2)(_reactive(kind=0, gamma=1.4), meso.cochran_chan(*NM))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0),
+                                  _reactive(kind=0, gamma=4.4, p_inf=6e8))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0), _reactive(cv=-1.0))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0), _reactive(arr_C=0.0))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0), _reactive(heat_Q=float("nan")))),
+    dict(mats=(meso.Material * 2)(meso.stiffened(1.4, 0.0), _reactive(reactive=2))),
+    # workspace sized for an inert state
+    dict(mats=reactive_pair(), ws=0x100000, ws_bytes=256 + 2 * 6 * 64 * 8 * 8),
     dict(opt=meso.Options(0.0, 1e-6, 0, 0, 1, 0)),
     dict(opt=meso.Options(1.5, 1e-6, 0, 0, 1, 0)),
     dict(opt=meso.Options(0.4, 0.6, 0, 0, 1, 0)),
