@@ -1,6 +1,6 @@
 /*
  * oracle.c -- plain FP64 CPU reference of the two-fluid diffuse-interface
- * finite-volume update (inert part of Eq. (1), Sec. 2.1; scheme of Sec. 3).
+ * finite-volume update (Eq. (1), Sec. 2.1; scheme of Sec. 3).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
  * this file; only the tests, the smoke check and the benchmark's CPU-baseline
@@ -20,6 +20,15 @@
  *     conservative update of the first five components and a non-conservative
  *     update of z1 (its advection equation in Eq. (1))         Sec. 3
  *   pointwise stage: z1 <- clamp(z1, eps, 1 - eps)             Sec. 3 (Strang)
+ *   liquid as a Cochran-Chan Mie-Grueneisen material, reference curves of
+ *     Eqs. (3)-(4), constants of Table 1                        Sec. 2.2
+ *   reactive liquid: reactant mass z2 rho2 lambda advected as a seventh
+ *     component (last line of Eq. (1)); Arrhenius source of Eq. (6) with the
+ *     constants of Table 3 at the liquid temperature of Eq. (5), applied as
+ *     S(dt/2) H(dt) S(dt/2) with the temperature frozen over each S
+ *   diagnostics: transverse averages (Sec. 4.2), domain integrals and the
+ *     remaining reactant mass (Eq. (10)), mass-weighted log-binned PDFs of
+ *     pressure, density and heat-release rate (Sec. 4.5)
  *
  * Built with -O2 -ffp-contract=off and no fast-math so that every operation is
  * a separately rounded IEEE double operation in the order written.

@@ -73,6 +73,37 @@ def test_uniform_lambda_stays_uniform_without_reaction():
     assert np.max(np.abs(lam - 0.7)) < 1e-13
 
 
+def test_smooth_lambda_advection_second_order():
+    """Without reaction (C = 0) a smooth lambda profile in liquid moving at
+    uniform u, p is a pure translation (last line of Eq. (1)); the
+    MUSCL-Hancock error of lambda falls at second order, which needs its own
+    Hancock predictor term."""
+    u0 = 100.0
+
+    def prof(x):
+        return 0.5 + 0.3 * np.sin(2 * np.pi * x)
+
+    errs = []
+    for n in (64, 128, 256):
+        dx = 1.0 / n
+        o = oracle.Oracle(rx_prob(n, dx=dx, rx=(0.0, TA, Q, CV), bc_xlo=1, bc_xhi=1))
+        x = (np.arange(n) + 0.5) * dx
+        prim = np.zeros((7, 1, n))
+        prim[0] = 1e-6
+        prim[1] = 1.2
+        prim[2] = R0
+        prim[3] = u0
+        prim[5] = 1e5
+        prim[6, 0] = prof(x)
+        o.set_primitive(prim)
+        o.run(10 ** 7, t_end=0.25 / u0)
+        lam = o.primitive()["lam"][0]
+        errs.append(np.mean(np.abs(lam - prof(x - u0 * o.t))))
+    e = np.array(errs)
+    order = np.log2(e[:-1] / e[1:])
+    assert np.all(order > 1.6), order
+
+
 def test_heat_release_field_and_pdf():
     sc = S.single_bubble(nx=60, ny=30, dx=1e-6, radius=6.0, centre=(34.0, 15.0), shock_x=20.0,
                          liquid="nm", p_shock=11.51e9, reactive=True)
