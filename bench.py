@@ -46,7 +46,8 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h"):
+    for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h",
+              "meso_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -116,7 +117,7 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
     {128^2, 256^2, 512^2}, `nsteps` steps each.  Sequential capacity first
     (solves back to back, one at a time, per-solve launches), then Poisson
     arrivals at 0.8x and 2x that capacity through the batched server and
-    through the sequential baseline."""
+    through the sequential baseline, and a burst of all requests at once."""
     from paper_1905_05727_amd import scenario, serve
     t = time.perf_counter()
     reqs = scenario.serving_workload(nreq, steps=nsteps)
@@ -135,14 +136,15 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
            "sequential_capacity_req_per_s": cap,
            "sequential_back_to_back_cell_updates_per_s": work / t_seq, "rates": {}}
     budget = 16 << 30
-    for mult in (0.8, 2.0):
-        arr = scenario.poisson_arrivals(nreq, mult * cap)
+    for mult in (0.8, 2.0, None):
+        # None: a burst -- every request arrives at t = 0 (capacity of each path)
+        arr = np.zeros(nreq) if mult is None else scenario.poisson_arrivals(nreq, mult * cap)
         with serve.Server(budget, max_slots=64, precision=precision, max_inflight=4) as srv:
             b = serve.serve(srv, reqs, arr, nsteps)
         sq = serve.serve_sequential(reqs, arr, nsteps, precision)
-        key = f"{mult}x"
+        key = "burst" if mult is None else f"{mult}x"
         out["rates"][key] = {
-            "arrival_rate_req_per_s": mult * cap,
+            "arrival_rate_req_per_s": None if mult is None else mult * cap,
             "batched": {"p50_ms": 1e3 * b["p50_s"], "p99_ms": 1e3 * b["p99_s"],
                         "cell_updates_per_s": b["cell_updates_per_s"],
                         "makespan_s": b["makespan_s"],
@@ -244,8 +246,9 @@ def main():
         "dtype": h["dtype"],
         "data": "synthetic",
         "config": {"workload": f"roofline case {sc.nx}x{sc.ny}: {sc.meta['nbubbles']} air "
-                               f"bubbles R~U[16,48] cells in water, 1 GPa planar shock, "
-                               f"CFL 0.4, seed {sc.meta['seed']}",
+                               f"bubbles R~U[16,48] cells in water (centre spacing >= 2.5 "
+                               f"mean diameters), 1 GPa planar shock, CFL 0.4, "
+                               f"seed {sc.meta['seed']}",
                    "cells": N, "precision": head, "parallelism": "single GPU",
                    "launch": r["launch"]},
         "roofline": {"bound": "alu", "achieved": h["alu_TOPs"], "peak": ALU_PEAK_TOPS,

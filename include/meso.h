@@ -1,12 +1,13 @@
 /*
  * meso.h -- C ABI of the MI355X two-fluid shock/bubble solver.
  *
- * The solver advances the inert two-phase Euler system of Eq. (1) (Sec. 2.1:
+ * The solver advances the two-phase Euler system of Eq. (1) (Sec. 2.1:
  * partial densities z1 rho1 and z2 rho2, momentum, total energy, and the
  * non-conservative advection of the air volume fraction z1) with the
- * pressure-equilibrium closure of Sec. 2.1 and stiffened-gas phases (the
+ * pressure-equilibrium closure of Sec. 2.1, stiffened-gas phases (the
  * Mie-Grueneisen form of Eq. (2) with constant reference terms, Sec. 2.2;
- * air as an ideal gas, Table 2).  The scheme is that of Sec. 3:
+ * air as an ideal gas, Table 2) or a Cochran-Chan liquid (Eqs. (2)-(4),
+ * Table 1).  The scheme is that of Sec. 3:
  * MUSCL-Hancock reconstruction with a van Leer (or minmod) slope limiter, HLLC
  * fluxes, dimensionally split sweeps, a CFL time step, and the pointwise stage
  * of the Strang split (z1 kept in [eps, 1 - eps]; for a reactive liquid also

@@ -3,20 +3,27 @@
 // without floating-point contraction for the FP64 mode; meso_kernels_fast.hip,
 // built with contraction for the FP32-bulk and FP32 modes).
 //
-// Equations: inert part of Eq. (1) (Sec. 2.1) -- partial densities, momentum,
-// total energy, non-conservative advection of the air volume fraction z1 --
-// with the pressure-equilibrium closure of Sec. 2.1 and stiffened-gas phases
-// (Eq. (2) with constant reference terms, Sec. 2.2).  Scheme of Sec. 3:
+// Equations: Eq. (1) (Sec. 2.1) -- partial densities, momentum, total energy,
+// non-conservative advection of the air volume fraction z1, and for a
+// reactive liquid the reactant mass z2 rho2 lambda -- with the
+// pressure-equilibrium closure of Sec. 2.1, stiffened-gas phases (Eq. (2)
+// with constant reference terms) or a Cochran-Chan liquid (Eqs. (2)-(4),
+// Sec. 2.2), and Arrhenius kinetics (Eq. (6)) at the liquid temperature of
+// Eq. (5).  Scheme of Sec. 3:
 // MUSCL-Hancock in primitive variables, van Leer or minmod slopes, HLLC flux
 // with the HLLC-consistent interface velocity for the z1 term, dimensionally
 // split sweeps (x then y on even steps, y then x on odd ones), CFL time step
-// and the pointwise stage of the Strang split (z1 clamp when inert).
+// and the pointwise stage of the Strang split (z1 clamp; reaction half-steps).
 //
 // Data layout in HBM: structure of arrays, 6 planes (z1 rho1, z2 rho2, rho u,
 // rho v, rho E, z1) -- 7 with the reactant mass z2 rho2 lambda of a reactive
 // liquid -- rows padded to a multiple of 64 elements; two state copies used as
 // ping-pong buffers.  NC (6 or 7) is the number of conserved components, a
 // template parameter so that the inert kernels carry no seventh component.
+// EOS (0 stiffened-gas liquid, 1 Cochran-Chan liquid) is a template parameter
+// of the step kernels for the same reason: the water kernels carry neither
+// the pow of the Cochran-Chan reference curves nor its registers.  EOS = -1
+// (the small kernels) selects the liquid at run time from the descriptor.
 //
 // Step kernel: a workgroup of 256 threads (4 wave64) owns a strip of 256
 // columns (252 written + 2 halo columns per side) and marches down a segment
@@ -158,7 +165,11 @@ __device__ __forceinline__ int map_idx(int i, int n, int bc_lo, int bc_hi) {
 // Closure (Sec. 2.1): sweep-frame conserved q = (a1, a2, mn, mt, E, z) to
 // primitives w = (a1, a2, un, ut, p, z), 1/rho and rho c^2; with NC = 7 also
 // q[6] = z2 rho2 lambda to w[6] = lambda, the liquid's unreacted mass fraction.
-template <class S, bool FAST, int NC>
+template <int EOS, class T> __device__ __forceinline__ bool is_cc(const Mix<T> &m) {
+    return EOS < 0 ? m.eos2 == 1 : EOS == 1;
+}
+
+template <class S, bool FAST, int NC, int EOS = -1>
 __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w[NC], S &r,
                                              S &rc2) {
     const S rho = q[0] + q[1];
@@ -166,7 +177,7 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w
     const S z2 = S(1) - z;
     const S xi = z * m.g1 + z2 * m.g2;
     S eta, psi = S(0);
-    if (m.eos2 == 1) {
+    if (is_cc<EOS>(m)) {
         S eta2;
         liquid_terms<S, FAST>(m, q[1], z2, eta2, psi);
         eta = z * m.h1 + eta2;
@@ -187,7 +198,7 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w
     const S ke = S(0.5) * (q[2] * un + q[3] * ut);
     const S rhoe = q[4] - ke;
     const S p = (rhoe - eta) * ixi;
-    if (m.eos2 == 1) rc2 = ((p * (S(1) + xi) + eta) - psi) * ixi;
+    if (is_cc<EOS>(m)) rc2 = ((p * (S(1) + xi) + eta) - psi) * ixi;
     else rc2 = (p * (S(1) + xi) + eta) * ixi;
     w[0] = q[0]; w[1] = q[1]; w[2] = un; w[3] = ut; w[4] = p; w[5] = z;
     if constexpr (NC == 7) w[6] = Ar<S, FAST>::div(q[6], q[1]);
@@ -235,7 +246,7 @@ template <class R, int NC> struct Side {
     R U[NC - 1], F[NC - 1];
 };
 
-template <class R, bool FAST, int NC>
+template <class R, bool FAST, int NC, int EOS>
 __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[NC], Side<R, NC> &s,
                                           R &c) {
     const R rho = w[0] + w[1];
@@ -243,7 +254,7 @@ __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[NC], Side<R
     const R z2 = R(1) - z;
     const R xi = z * m.g1 + z2 * m.g2;
     R eta, num;
-    if (m.eos2 == 1) {
+    if (is_cc<EOS>(m)) {
         R eta2, psi2;
         liquid_terms<R, FAST>(m, w[1], z2, eta2, psi2);
         eta = z * m.h1 + eta2;
@@ -297,13 +308,13 @@ __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out
 // NC = 7, the reactant-mass flux.  The star state is evaluated once, for the
 // side the contact moves away from; only faces with S* == 0 exactly evaluate
 // both sides and average.
-template <class R, bool FAST, int NC>
+template <class R, bool FAST, int NC, int EOS>
 __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR[NC],
                                      R out[NC + 1]) {
     Side<R, NC> L, Rs;
     R cL, cR;
-    side_eval<R, FAST, NC>(m, wL, L, cL);
-    side_eval<R, FAST, NC>(m, wR, Rs, cR);
+    side_eval<R, FAST, NC, EOS>(m, wL, L, cL);
+    side_eval<R, FAST, NC, EOS>(m, wR, Rs, cR);
     const R SL = fmin(L.un - cL, Rs.un - cR);
     const R SR = fmax(L.un + cL, Rs.un + cR);
     const R dL = SL - L.un;
@@ -358,12 +369,12 @@ __device__ __forceinline__ void update_cell(const S q[NC], const R flo[NC + 1],
 // x sweep of one row of the strip.  All 256 threads call it (it holds
 // barriers); q: this thread's cell, qo: updated cell (valid for threads
 // 2..253; the halo threads return q unchanged).
-template <class S, class R, bool FAST, int LIM, int NC>
+template <class S, class R, bool FAST, int LIM, int NC, int EOS>
 __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R hl,
                                       const Mix<S> &ms, const Mix<R> &mr,
                                       R (*sWF)[kThreads], R (*sH)[kThreads]) {
     S w[NC], r, rc2;
-    cons_to_prim<S, FAST, NC>(ms, q, w, r, rc2);
+    cons_to_prim<S, FAST, NC, EOS>(ms, q, w, r, rc2);
     R wr[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -389,7 +400,7 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
         R whm[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) whm[c] = sH[c][t - 1];
-        hllc<R, FAST, NC>(mr, whm, wl, f);
+        hllc<R, FAST, NC, EOS>(mr, whm, wl, f);
 #pragma unroll
         for (int c = 0; c < NC + 1; ++c) sWF[c][t] = f[c];
     }
@@ -409,7 +420,7 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
 // y sweep as a rolling window down one column (registers only).  Rows are
 // pushed in order; after the 5th row the window yields the updated row two
 // behind the one pushed.  Values are in the y frame (normal momentum rho v).
-template <class S, class R, bool FAST, int LIM, int NC>
+template <class S, class R, bool FAST, int LIM, int NC, int EOS>
 struct YPipe {
     S q1[NC], q2[NC];    // conserved rows k-1, k-2
     R w1[NC], w2[NC];    // primitives rows k-1, k-2
@@ -421,7 +432,7 @@ struct YPipe {
     __device__ __forceinline__ bool push(int cnt, const S qk[NC], S qo[NC], S lam, R hl,
                                          const Mix<S> &ms, const Mix<R> &mr) {
         S w[NC], r, rc2;
-        cons_to_prim<S, FAST, NC>(ms, qk, w, r, rc2);
+        cons_to_prim<S, FAST, NC, EOS>(ms, qk, w, r, rc2);
         R wk[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) wk[c] = (R)w[c];
@@ -431,7 +442,7 @@ struct YPipe {
             face_states<R, FAST, LIM, NC>(w2, w1, wk, r1, c1, hl, wl, wh);
             if (cnt >= 3) {
                 R f[NC + 1];
-                hllc<R, FAST, NC>(mr, wh2, wl, f);
+                hllc<R, FAST, NC, EOS>(mr, wh2, wl, f);
                 if (cnt >= 4) {
                     update_cell<S, R, NC>(q2, f2, f, lam, qo);
                     out = true;
@@ -469,7 +480,7 @@ template <class S, bool FAST>
 __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S h) {
     if (!(q[6] > S(0))) return;
     S w[7], r, rc2;
-    cons_to_prim<S, FAST, 7>(m, q, w, r, rc2);
+    cons_to_prim<S, FAST, 7, 1>(m, q, w, r, rc2);
     const S rho2 = Ar<S, FAST>::div(q[1], S(1) - q[5]);
     const S v = Ar<S, FAST>::div(m.rho0, rho2);
     S vc, vd;
@@ -485,13 +496,13 @@ __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S
 
 // Pointwise stage and CFL contribution of one updated cell (U order): the z1
 // clamp, the second half of the reaction (NC = 7), then the signal speed.
-template <class S, bool FAST, int NC>
+template <class S, bool FAST, int NC, int EOS>
 __device__ __forceinline__ void epilogue(S q[NC], const Mix<S> &ms, const Rx<S> &rx, S hdt,
                                          S zlo, S zhi, S idx, S idy, S &smax, int &bad) {
     q[5] = fmin(fmax(q[5], zlo), zhi);
     if constexpr (NC == 7) react<S, FAST>(q, ms, rx, hdt);
     S w[NC], r, rc2;
-    cons_to_prim<S, FAST, NC>(ms, q, w, r, rc2);
+    cons_to_prim<S, FAST, NC, EOS>(ms, q, w, r, rc2);
     const S c = Ar<S, FAST>::sqrt_(rc2 * r);
     const S s = fmax((fabs(w[2]) + c) * idx, (fabs(w[3]) + c) * idy);
     if (!(r > S(0)) || !(rc2 > S(0)) || !(s <= Ar<S, FAST>::big())) bad = 1;
@@ -535,7 +546,7 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // of two sweeps) applies the first half of the reaction stage (NC = 7) to
 // every value it loads, halo cells included.  All threads of the workgroup
 // call it.
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC>
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
                                          R (*sWF)[kThreads], R (*sH)[kThreads]) {
     Control *ctl = d.ctl;
@@ -577,7 +588,7 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
         if constexpr (NC == 7 && kStarts) react<S, FAST>(q, ms, rx, hdt);
     };
     auto store = [&](int k, S q[NC]) {
-        if (FINAL) epilogue<S, FAST, NC>(q, ms, rx, hdt, zlo, zhi, idx, idy, smax, bad);
+        if (FINAL) epilogue<S, FAST, NC, EOS>(q, ms, rx, hdt, zlo, zhi, idx, idy, smax, bad);
         const long long o = (long long)k * d.pitch + col;
 #pragma unroll
         for (int c = 0; c < NC; ++c) dst[c * plane + o] = q[c];
@@ -592,11 +603,11 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             for (int c = 0; c < NC; ++c) q[c] = qn[c];
             if (k + 1 < y1) load(k + 1, qn);
             start(q);
-            x_row<S, R, FAST, LIM, NC>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            x_row<S, R, FAST, LIM, NC, EOS>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
             if (out_col) store(k, qo);
         }
     } else {
-        YPipe<S, R, FAST, LIM, NC> yp;
+        YPipe<S, R, FAST, LIM, NC, EOS> yp;
         const int k0 = y0 - kHalo, k1 = y1 + kHalo;
         S qn[NC];
         load(k0, qn);
@@ -609,7 +620,7 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             start(q);
             if (MODE == kXY) {
                 S qs[NC], qy[NC], qo[NC], qu[NC];
-                x_row<S, R, FAST, LIM, NC>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                x_row<S, R, FAST, LIM, NC, EOS>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
                 to_yframe<S, NC>(qs, qy);
                 if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
                     to_yframe<S, NC>(qo, qu);
@@ -624,7 +635,7 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
                     if (got && out_col) store(k - kHalo, qu);
                 } else if (got) {  // kYX: x sweep of the row just finished in y
                     S qx[NC];
-                    x_row<S, R, FAST, LIM, NC>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    x_row<S, R, FAST, LIM, NC, EOS>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
                     if (out_col) store(k - kHalo, qx);
                 }
             }
@@ -634,18 +645,19 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
 }
 
 // State update of one solve: grid (strips, segments).
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC = 6>
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
 __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
     __shared__ R sWF[NC + 1][kThreads];
     __shared__ R sH[NC][kThreads];
     if (d.ctl->skip) return;
-    run_tile<S, R, FAST, LIM, MODE, FINAL, NC>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
+    run_tile<S, R, FAST, LIM, MODE, FINAL, NC, EOS>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
 }
 
 // Fused state update of many solves in one launch: workgroup b takes tile
 // tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
 // (x-y order and source copy), read from its control block.  Inert solves
-// only (NC = 6).
+// only (NC = 6); the liquid is chosen per tile (EOS from the solve's
+// descriptor), so this kernel holds both liquid variants.
 template <class S, class R, bool FAST, int LIM>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
                                                                 const int4 *tiles) {
@@ -655,40 +667,46 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *desc
     const Desc d = descs[tl.x];
     if (d.ctl->skip) return;
     const int par = (int)(d.ctl->step_exec & 1);
-    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6>(d, tl.y, tl.z, 0, sWF, sH);
-    else run_tile<S, R, FAST, LIM, kYX, true, 6>(d, tl.y, tl.z, 1, sWF, sH);
+    if (d.eos2 == 1) {
+        if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, 1>(d, tl.y, tl.z, 0, sWF, sH);
+        else run_tile<S, R, FAST, LIM, kYX, true, 6, 1>(d, tl.y, tl.z, 1, sWF, sH);
+    } else {
+        if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, 0>(d, tl.y, tl.z, 0, sWF, sH);
+        else run_tile<S, R, FAST, LIM, kYX, true, 6, 0>(d, tl.y, tl.z, 1, sWF, sH);
+    }
 }
 
 // Host-side launch of the step kernel variant for one sweep mode (kXY, kYX,
 // or a single sweep kX / kY that does or does not end the step).
-template <class S, class R, bool FAST, int LIM, int NC>
-void launch_step_variants(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
+template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
+    void (*k)(Desc, int);
     switch (mode) {
-        case kXY:
-            hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kXY, true, NC>), grid, block, 0, st,
-                               d, src);
-            break;
-        case kYX:
-            hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kYX, true, NC>), grid, block, 0, st,
-                               d, src);
-            break;
+        case kXY: k = step_kernel<S, R, FAST, LIM, kXY, true, NC, EOS>; break;
+        case kYX: k = step_kernel<S, R, FAST, LIM, kYX, true, NC, EOS>; break;
         case kX:
-            if (final_pass)
-                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, true, NC>), grid, block, 0,
-                                   st, d, src);
-            else
-                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kX, false, NC>), grid, block, 0,
-                                   st, d, src);
+            k = final_pass ? step_kernel<S, R, FAST, LIM, kX, true, NC, EOS>
+                           : step_kernel<S, R, FAST, LIM, kX, false, NC, EOS>;
             break;
         default:
-            if (final_pass)
-                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, true, NC>), grid, block, 0,
-                                   st, d, src);
-            else
-                hipLaunchKernelGGL((step_kernel<S, R, FAST, LIM, kY, false, NC>), grid, block, 0,
-                                   st, d, src);
+            k = final_pass ? step_kernel<S, R, FAST, LIM, kY, true, NC, EOS>
+                           : step_kernel<S, R, FAST, LIM, kY, false, NC, EOS>;
             break;
+    }
+    hipLaunchKernelGGL(k, grid, block, 0, st, d, src);
+}
+
+// Liquid chosen from the descriptor: a reactive solve is always Cochran-Chan.
+template <class S, class R, bool FAST, int LIM, int NC>
+void launch_step_variants(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
+    if constexpr (NC == 7) {
+        launch_step_variants_eos<S, R, FAST, LIM, 7, 1>(d, mode, final_pass, src, st);
+    } else {
+        if (d.eos2 == 1)
+            launch_step_variants_eos<S, R, FAST, LIM, NC, 1>(d, mode, final_pass, src, st);
+        else
+            launch_step_variants_eos<S, R, FAST, LIM, NC, 0>(d, mode, final_pass, src, st);
     }
 }
 

@@ -343,10 +343,12 @@ def roofline_8192(seed: int = SEEDS["roofline_8192"], n: int = 8192) -> Scenario
 
 
 def serving_request(rng: np.random.Generator, sizes=(128, 256, 512), steps: int = 500,
-                    eps: float = Z_EPS) -> Scenario:
+                    eps: float = Z_EPS, centre_factor: float = 2.0) -> Scenario:
     """One independent shock-bubble solve of the serving workload: square grid
     drawn from `sizes`, 1-8 bubbles of radius U[0.05, 0.15] x width with edge
-    gap >= 2 cells, shock pressure U[0.5, 2] GPa; placement retried."""
+    gap >= 2 cells and centre spacing >= centre_factor mean diameters of each
+    pair (2: edge gaps of at least the sum of the radii, so no thin water gap
+    fails under the shock), shock pressure U[0.5, 2] GPa; placement retried."""
     n = int(rng.choice(sizes))
     nb = int(rng.integers(1, 9))
     p_shock = float(rng.uniform(0.5e9, 2.0e9))
@@ -355,7 +357,7 @@ def serving_request(rng: np.random.Generator, sizes=(128, 256, 512), steps: int 
         try:
             sub = np.random.default_rng(sub_seed + attempt)
             b = place_bubbles(sub, nb, n, n, 0.05 * n, 0.15 * n, 2.0, x_lo=16.0,
-                              max_draws=20000)
+                              max_draws=20000, centre_factor=centre_factor)
             break
         except RuntimeError:
             continue
@@ -368,10 +370,11 @@ def serving_request(rng: np.random.Generator, sizes=(128, 256, 512), steps: int 
 
 
 def serving_workload(nreq: int = 256, seed: int = SEEDS["serving"], sizes=(128, 256, 512),
-                     steps: int = 500):
+                     steps: int = 500, centre_factor: float = 2.0):
     """The list of serving requests, reproducible from `seed`."""
     rng = np.random.default_rng(seed)
-    return [serving_request(rng, sizes=sizes, steps=steps) for _ in range(nreq)]
+    return [serving_request(rng, sizes=sizes, steps=steps, centre_factor=centre_factor)
+            for _ in range(nreq)]
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = SEEDS["serving"]) -> np.ndarray:
