@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=8192, help="grid size (n x n)")
     ap.add_argument("--modes", default="fp64,fp32_fp64acc,fp32")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
@@ -220,6 +220,10 @@ def main():
              "kernel_ms": r["kernel_ms_avg"], "hbm_algorithmic_GBs": ach,
              "hbm_frac": ach / HBM_PEAK_GBS, "alu_TOPs": ops, "alu_frac": ops / ALU_PEAK_TOPS,
              "dtype": DTYPE[m]}
+        tb = traffic_from_profiles(m)
+        if tb is not None:      # counted HBM bytes of the same kernel / its time here
+            d["hbm_measured_GBs"] = tb / (r["kernel_ms_avg"] * 1e-3) / 1e9
+            d["hbm_measured_frac"] = d["hbm_measured_GBs"] / HBM_PEAK_GBS
         if ref is not None and m != "fp64":
             for k in ("rho", "p"):
                 d[f"rel_l1_{k}_vs_fp64"] = float(np.abs(r["fields"][k] - ref["fields"][k]).sum()
@@ -258,6 +262,7 @@ def main():
                      "ops_per_cell": OPS_PER_CELL,
                      "hbm": {"achieved_GBs": h["hbm_algorithmic_GBs"], "peak_GBs": HBM_PEAK_GBS,
                              "frac": h["hbm_frac"], "bytes_per_cell": BYTES_PER_CELL[head],
+                             "measured_GBs": h.get("hbm_measured_GBs"),
                              "copy_kernel_GBs": cp["GBs"]}},
         "modes": mode_out,
     }

@@ -94,6 +94,28 @@ def test_fp64_bubble_bitwise(shape, limiter, fused):
             assert_bitwise(s.read_conserved(), o.U, f"after {upto} steps")
 
 
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 3), (3, 2), (4, 4)])
+def test_fp64_degenerate_grids_bitwise(shape, bc):
+    """Grids smaller than the stencil (a periodic wrap of 1-3 cells, a single
+    row or column): the halo index map and the ragged tile must still give
+    the oracle's state."""
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 31 + ny)
+    prim = S.uniform_state(nx, ny, dx=1e-3)
+    prim[0] = rng.uniform(0.2, 0.8, (ny, nx))
+    prim[3] = rng.uniform(-20.0, 20.0, (ny, nx))
+    prim[4] = rng.uniform(-20.0, 20.0, (ny, nx))
+    prim[5] = 1e5 * rng.uniform(0.9, 1.1, (ny, nx))
+    sc = S.Scenario("degenerate", nx, ny, 1e-3, 1e-3, prim, bc=(bc,) * 4)
+    say(f"case: degenerate grid {nx}x{ny} {bc}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(7)
+        o.run(7)
+        assert_bitwise(s.read_conserved(), o.U, f"{nx}x{ny} {bc}")
+
+
 @pytest.mark.parametrize("limiter", ["vanleer", "minmod"])
 def test_fp64_periodic_bitwise(limiter):
     sc = bubble(270, 70, periodic=True, limiter=limiter)
@@ -114,6 +136,21 @@ def test_fp64_single_bubble_full_size_bitwise():
         s.run_steps(12)
         o.run(12)
         assert_bitwise(s.read_conserved(), o.U, "1024x512")
+
+
+def test_fp64_single_bubble_2000_steps_bitwise():
+    """The single-bubble workload (1024 x 512, 1 GPa, R = 64 cells) over its
+    full 2000 steps: the FP64 GPU state equals the oracle's bit for bit."""
+    sc = S.single_bubble()
+    say("case: single bubble 1024x512, 2000 steps, FP64 vs oracle")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(2000)
+        U = s.read_conserved()
+        t, n, _ = s.time()
+    o.run(2000)
+    assert n == 2000 and t == o.t
+    assert_bitwise(U, o.U, "1024x512 after 2000 steps")
 
 
 def test_fp64_explicit_dt_and_resume():
