@@ -314,6 +314,13 @@ int32_t mf_server_tick(mf_server *srv, int32_t *active, int32_t *queued);
 /* State of a request (MF_REQ_*); MF_E_INVALID_ARG for an unknown ticket. */
 int32_t mf_server_poll(mf_server *srv, uint64_t ticket, int32_t *state);
 
+/* Tickets of requests that reached MF_REQ_DONE or MF_REQ_FAILED since they were
+ * last reported here, oldest first: up to `capacity` of them are written to
+ * tickets[] (host array owned by the caller) and their number to *count; the
+ * rest are kept for the next call.  Each ticket is reported once.  Lets a
+ * serving loop find finished work without polling every outstanding ticket. */
+int32_t mf_server_finished(mf_server *srv, uint64_t *tickets, int32_t capacity, int32_t *count);
+
 /* Copy a finished request's 6 conserved planes (6*nx*ny doubles), its final
  * time and step count, and forget the request.  MF_E_NOT_READY while it runs,
  * MF_E_NONFINITE_STATE if its state became non-physical (the ticket is then

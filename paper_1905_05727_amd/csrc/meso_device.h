@@ -50,7 +50,9 @@ namespace meso {
 
 // ------------------------------------------------------------------------
 // Arithmetic policies.  Ar<double, false>: IEEE division and square root (the
-// FP64 mode, bit-compatible with the arithmetic contract).  Ar<double, true>:
+// FP64 mode, bit-compatible with the arithmetic contract; the two powers of
+// the Cochran-Chan reference curves share one logarithm, v^-C = exp(-C ln v),
+// a few ulp from a correctly rounded pow).  Ar<double, true>:
 // hardware reciprocal refined by one Newton step and the hardware square
 // root (the FP64 closure of the FP32-bulk mode).  Ar<float, *>: hardware
 // reciprocal and square root.
@@ -59,8 +61,9 @@ template <> struct Ar<double, false> {
     // v^-C and v^-D of the Cochran-Chan reference curves
     static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
                                               double &vd) {
-        vc = pow(v, -C);
-        vd = pow(v, -D);
+        const double l = log(v);
+        vc = exp(-C * l);
+        vd = exp(-D * l);
     }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
@@ -71,8 +74,9 @@ template <> struct Ar<double, false> {
 template <> struct Ar<double, true> {
     static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
                                               double &vd) {
-        vc = pow(v, -C);
-        vd = pow(v, -D);
+        const double l = log(v);
+        vc = exp(-C * l);
+        vd = exp(-D * l);
     }
     static __device__ __forceinline__ double rcp(double a) {
         const double r = __builtin_amdgcn_rcp(a);

@@ -122,6 +122,7 @@ struct mf_server {
     std::vector<Slot> slots;
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Request> reqs;
+    std::deque<uint64_t> finished;    // tickets done or failed, not yet reported
     uint64_t next_id;
     // batched launch tables
     Desc *d_descs;
@@ -355,6 +356,7 @@ int32_t harvest(mf_server *s, bool wait) {
         r.t_final = c.t;
         r.steps_final = c.step;
         r.state = c.err ? MF_REQ_FAILED : MF_REQ_DONE;
+        s->finished.push_back(sl.req);
         s->rb_free.push_back(sl.pin);
         s->ev_pool.push_back(sl.done);
         s->fl.release(sl.off, sl.bytes);
@@ -502,6 +504,19 @@ int32_t mf_server_poll(mf_server *s, uint64_t ticket, int32_t *state) {
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return MF_E_INVALID_ARG;
     *state = it->second.state;
+    return MF_OK;
+}
+
+int32_t mf_server_finished(mf_server *s, uint64_t *tickets, int32_t capacity, int32_t *count_out) {
+    if (!s || !count_out || capacity < 0 || (capacity > 0 && !tickets)) return MF_E_INVALID_ARG;
+    int32_t rc = harvest(s, false);
+    if (rc != MF_OK) return rc;
+    int32_t n = 0;
+    while (n < capacity && !s->finished.empty()) {
+        tickets[n++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    *count_out = n;
     return MF_OK;
 }
 

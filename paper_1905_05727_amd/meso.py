@@ -33,7 +33,8 @@ EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conser
            "mf_kernel_time", "mf_launch_info", "mf_y_averages", "mf_integrals",
            "mf_log_histogram", "mf_destroy", "mf_status_str", "mf_version",
            "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
-           "mf_server_poll", "mf_server_result", "mf_server_drain", "mf_server_get_stats",
+           "mf_server_poll", "mf_server_finished", "mf_server_result", "mf_server_drain",
+           "mf_server_get_stats",
            "mf_server_destroy"]
 
 
@@ -147,6 +148,7 @@ def load_library():
                                          C.POINTER(C.c_uint64)]),
         "mf_server_tick": (C.c_int32, [P, I32, I32]),
         "mf_server_poll": (C.c_int32, [P, C.c_uint64, I32]),
+        "mf_server_finished": (C.c_int32, [P, C.POINTER(C.c_uint64), C.c_int32, I32]),
         "mf_server_result": (C.c_int32, [P, C.c_uint64, D, C.c_size_t, D, I64]),
         "mf_server_drain": (C.c_int32, [P]),
         "mf_server_get_stats": (C.c_int32, [P, C.POINTER(ServerStats)]),

@@ -65,6 +65,14 @@ class Server:
         meso._chk("mf_server_poll", self._lib.mf_server_poll(self._h, ticket, C.byref(st)))
         return st.value
 
+    def finished(self, capacity: int = 1024) -> list:
+        """Tickets that finished (done or failed) since the last call."""
+        buf = (C.c_uint64 * capacity)()
+        n = C.c_int32()
+        meso._chk("mf_server_finished", self._lib.mf_server_finished(self._h, buf, capacity,
+                                                                      C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
     def result(self, ticket: int):
         ny, nx = self._shape.pop(ticket)
         out = np.empty((6, ny, nx), dtype=np.float64)
@@ -122,14 +130,12 @@ def serve(server: Server, requests, arrivals, nsteps: int, keep_results: bool = 
             time.sleep(max(0.0, min(arrivals[i] - now, 0.01)))
             continue
         server.tick()
-        for tk in list(outstanding):
-            st = server.poll(tk)
-            if st in (REQ_DONE, REQ_FAILED):
-                k = outstanding.pop(tk)
-                U, tf, steps = server.result(tk)
-                lat[k] = time.perf_counter() - t0 - arrivals[k]
-                if keep_results:
-                    results[k] = (U, tf, steps)
+        for tk in server.finished():
+            k = outstanding.pop(tk)
+            U, tf, steps = server.result(tk)
+            lat[k] = time.perf_counter() - t0 - arrivals[k]
+            if keep_results:
+                results[k] = (U, tf, steps)
     makespan = time.perf_counter() - t0
     work = float(sum(r.nx * r.ny for r in requests)) * nsteps
     out = {"p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99), "mean_s": float(lat.mean()),

@@ -56,6 +56,22 @@ def test_alone_equals_in_mix(prec):
         assert np.array_equal(o.U, got[0][0])
 
 
+def test_finished_reports_each_ticket_once():
+    reqs = small_requests(5, seed=13, sizes=(64, 100))
+    say("case: finished tickets, 5 requests")
+    with serve.Server(1 << 28, max_slots=3, precision="fp32_fp64acc") as srv:
+        tks = [srv.submit(sc, 9) for sc in reqs]
+        seen = []
+        while len(seen) < len(tks):
+            srv.tick()
+            seen += srv.finished()
+        assert sorted(seen) == sorted(tks) and len(set(seen)) == len(tks)
+        assert srv.finished() == []
+        for tk in tks:
+            assert srv.poll(tk) == serve.REQ_DONE
+            srv.result(tk)
+
+
 def test_admission_stays_within_budget():
     reqs = small_requests(6, seed=11, sizes=(200,))
     per = serve.Server.request_bytes(200, 200, "fp32_fp64acc")
