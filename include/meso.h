@@ -324,7 +324,8 @@ int32_t mf_server_finished(mf_server *srv, uint64_t *tickets, int32_t capacity, 
 /* Copy a finished request's 6 conserved planes (6*nx*ny doubles), its final
  * time and step count, and forget the request.  MF_E_NOT_READY while it runs,
  * MF_E_NONFINITE_STATE if its state became non-physical (the ticket is then
- * released as well). */
+ * released as well).  Until its result is taken, a finished request holds a
+ * pinned host buffer of its size. */
 int32_t mf_server_result(mf_server *srv, uint64_t ticket, double *out_cons, size_t count,
                          double *t, int64_t *steps);
 

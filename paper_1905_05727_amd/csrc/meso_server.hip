@@ -14,6 +14,13 @@
 // last step has been enqueued is converted to dense FP64 on the compute stream
 // and copied to pinned host memory on the read-back stream, overlapping the
 // following ticks.
+//
+// Host memory: a submitted request's primitive planes are copied once, into a
+// pinned upload buffer from a pool, and go to the device straight from it; a
+// finished request keeps its pinned read-back buffer until mf_server_result
+// copies it into the caller's array.  Pooled buffers are reused by later
+// requests, so a steady stream of requests neither allocates nor page-faults
+// host memory.
 
 #include "meso.h"
 #include "meso_internal.h"
@@ -40,10 +47,10 @@ struct Request {
     mf_grid grid;
     mf_material mat[2];
     mf_options opt;
-    std::vector<double> prim;     // until admitted
+    int up;                       // pinned upload buffer (primitive planes) until admitted
     int64_t nsteps;
     int state;                    // MF_REQ_*
-    std::vector<double> result;   // 6 planes once done
+    int rb;                       // pinned read-back buffer (6 planes) once done
     double t_final;
     int64_t steps_final;
 };
@@ -134,12 +141,14 @@ struct mf_server {
     int n_active;
     int n_tiles;
     int64_t active_cells;
-    // uploads of initial states
+    // uploads of initial states: pinned buffers, filled at submission, free
+    // again once their copy to the device has been enqueued
     double *d_stage;
     size_t stage_bytes;
     std::vector<Pinned> up_pins;
-    size_t up_next;
-    // read-back pinned buffers
+    std::vector<int> up_free;
+    // read-back pinned buffers, held by a finished request until its result
+    // is taken
     std::vector<Pinned> rb_pins;
     std::vector<int> rb_free;
     // in-flight tick events
@@ -183,6 +192,36 @@ int32_t ring_pinned(std::vector<Pinned> &ring, size_t &next, size_t bytes, Pinne
     return MF_OK;
 }
 
+// A pinned buffer of at least `bytes` from a pool: the smallest free one that
+// fits (after its last asynchronous copy), else a new one.
+int32_t pool_pinned(std::vector<Pinned> &pool, std::vector<int> &freel, size_t bytes, int *out) {
+    int best = -1;
+    for (size_t i = 0; i < freel.size(); ++i) {
+        const Pinned &p = pool[freel[i]];
+        if (p.bytes >= bytes && (best < 0 || p.bytes < pool[freel[best]].bytes)) best = (int)i;
+    }
+    if (best >= 0) {
+        const int k = freel[best];
+        freel.erase(freel.begin() + best);
+        if (pool[k].ev && hipEventSynchronize(pool[k].ev) != hipSuccess) return MF_E_DEVICE;
+        *out = k;
+        return MF_OK;
+    }
+    Pinned p{nullptr, 0, nullptr};
+    if (hipHostMalloc((void **)&p.p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return MF_E_OUT_OF_MEMORY;
+    }
+    if (hipEventCreateWithFlags(&p.ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(p.p);
+        return MF_E_DEVICE;
+    }
+    p.bytes = bytes;
+    pool.push_back(p);
+    *out = (int)pool.size() - 1;
+    return MF_OK;
+}
+
 size_t request_bytes(const mf_grid *g, int prec) {
     return meso::kAlign + 2 * meso::state_bytes(g, prec, 6) + readback_bytes(g);
 }
@@ -204,13 +243,11 @@ int32_t admit_one(mf_server *s, Request &r, Slot &sl) {
         }
         s->stage_bytes = bytes;
     }
-    Pinned *pp = nullptr;
-    int32_t rc = ring_pinned(s->up_pins, s->up_next, bytes, &pp);
-    if (rc != MF_OK) return rc;
-    memcpy(pp->p, r.prim.data(), bytes);
-    std::vector<double>().swap(r.prim);
-    hipError_t e = hipMemcpyAsync(s->d_stage, pp->p, bytes, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipEventRecord(pp->ev, s->st);
+    Pinned &pp = s->up_pins[r.up];
+    hipError_t e = hipMemcpyAsync(s->d_stage, pp.p, bytes, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipEventRecord(pp.ev, s->st);
+    s->up_free.push_back(r.up);   // reusable once that copy has run
+    r.up = -1;
     if (e == hipSuccess) e = meso::launch_init_control(sl.d, 0.0, 0, s->st);
     if (e == hipSuccess) e = meso::launch_prim_to_cons(sl.d, s->cfg.precision, 0, s->d_stage, s->st);
     if (e == hipSuccess) e = meso::launch_reduce(sl.d, s->cfg.precision, 0, s->st);
@@ -299,23 +336,8 @@ int32_t start_drain(mf_server *s, Slot &sl) {
     const size_t bytes = 6 * n * sizeof(double) + sizeof(Control);
     // a free pinned read-back buffer
     int pin = -1;
-    for (size_t i = 0; i < s->rb_free.size(); ++i) {
-        if (s->rb_pins[s->rb_free[i]].bytes >= bytes) {
-            pin = s->rb_free[i];
-            s->rb_free.erase(s->rb_free.begin() + i);
-            break;
-        }
-    }
-    if (pin < 0) {
-        Pinned p{nullptr, 0, nullptr};
-        if (hipHostMalloc((void **)&p.p, bytes, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            return MF_E_OUT_OF_MEMORY;
-        }
-        p.bytes = bytes;
-        s->rb_pins.push_back(p);
-        pin = (int)s->rb_pins.size() - 1;
-    }
+    int32_t rc = pool_pinned(s->rb_pins, s->rb_free, bytes, &pin);
+    if (rc != MF_OK) return rc;
     sl.pin = pin;
     sl.draining = true;
     double *dense = (double *)(s->arena + sl.off + meso::kAlign + 2 * meso::state_bytes(&r.grid, s->cfg.precision, 6));
@@ -350,14 +372,14 @@ int32_t harvest(mf_server *s, bool wait) {
         Request &r = s->reqs[sl.req];
         const size_t n = (size_t)r.grid.nx * r.grid.ny;
         const double *hp = s->rb_pins[sl.pin].p;
-        r.result.assign(hp, hp + 6 * n);
         Control c;
         memcpy(&c, hp + 6 * n, sizeof(Control));
         r.t_final = c.t;
         r.steps_final = c.step;
         r.state = c.err ? MF_REQ_FAILED : MF_REQ_DONE;
         s->finished.push_back(sl.req);
-        s->rb_free.push_back(sl.pin);
+        if (c.err) s->rb_free.push_back(sl.pin);   // nothing to hand back
+        else r.rb = sl.pin;                          // held until the result is taken
         s->ev_pool.push_back(sl.done);
         s->fl.release(sl.off, sl.bytes);
         sl.used = false;
@@ -418,11 +440,9 @@ int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_serve
     for (auto &sl : s->slots) sl.used = false;
     const int ring = cfg->max_inflight + 2;
     for (int i = 0; i < ring; ++i) {
-        Pinned a{nullptr, 0, nullptr}, b{nullptr, 0, nullptr};
+        Pinned a{nullptr, 0, nullptr};
         (void)hipEventCreateWithFlags(&a.ev, hipEventDisableTiming);
-        (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
         s->tab_pins.push_back(a);
-        s->up_pins.push_back(b);
     }
     *out = s;
     return MF_OK;
@@ -447,7 +467,12 @@ int32_t mf_server_submit(mf_server *s, const mf_grid *grid, const mf_material ma
     r.opt = *opt;
     r.opt.fused = 1;
     const size_t n = (size_t)grid->nx * grid->ny * 6;
-    r.prim.assign(prim, prim + n);
+    int up = -1;
+    const int32_t rc = pool_pinned(s->up_pins, s->up_free, n * sizeof(double), &up);
+    if (rc != MF_OK) return rc;
+    memcpy(s->up_pins[up].p, prim, n * sizeof(double));
+    r.up = up;
+    r.rb = -1;
     r.nsteps = nsteps;
     r.state = MF_REQ_QUEUED;
     r.t_final = 0.0;
@@ -535,7 +560,8 @@ int32_t mf_server_result(mf_server *s, uint64_t ticket, double *out_cons, size_t
     }
     const size_t n = (size_t)r.grid.nx * r.grid.ny * 6;
     if (!out_cons || count_ != n) return MF_E_INVALID_ARG;
-    memcpy(out_cons, r.result.data(), n * sizeof(double));
+    memcpy(out_cons, s->rb_pins[r.rb].p, n * sizeof(double));
+    s->rb_free.push_back(r.rb);
     if (t) *t = r.t_final;
     if (steps) *steps = r.steps_final;
     s->reqs.erase(it);

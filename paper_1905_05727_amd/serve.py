@@ -1,9 +1,10 @@
 """Serving loop over the continuous-batching server of the C ABI.
 
 ``Server`` marshals the mf_server_* calls.  ``serve`` replays a list of
-requests with given arrival times: requests are submitted when they arrive,
-and every loop iteration runs one scheduling tick (admission into free slots
-within the HBM budget + one batched step of everything admitted); latency is
+requests with given arrival times: requests are submitted when they arrive (a
+few per iteration), every loop iteration runs one scheduling tick (admission
+into free slots within the HBM budget + one batched step of everything
+admitted) and collects the requests the server reports finished; latency is
 arrival -> result on the host.  ``serve_sequential`` is the baseline: the same
 requests served first come, first served, one solve at a time with its own
 per-step launches.
@@ -73,9 +74,13 @@ class Server:
                                                                       C.byref(n)))
         return [buf[i] for i in range(n.value)]
 
-    def result(self, ticket: int):
+    def result(self, ticket: int, out: np.ndarray | None = None):
+        """(conserved planes, final time, steps) of a finished request; `out`
+        (C-contiguous float64 of shape (6, ny, nx)) is filled if given."""
         ny, nx = self._shape.pop(ticket)
-        out = np.empty((6, ny, nx), dtype=np.float64)
+        if out is None:
+            out = np.empty((6, ny, nx), dtype=np.float64)
+        assert out.shape == (6, ny, nx) and out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
         t = C.c_double()
         n = C.c_int64()
         meso._chk("mf_server_result", self._lib.mf_server_result(self._h, ticket, meso._dptr(out),
@@ -112,27 +117,39 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
 
 
-def serve(server: Server, requests, arrivals, nsteps: int, keep_results: bool = False) -> dict:
+def serve(server: Server, requests, arrivals, nsteps: int, keep_results: bool = False,
+          submit_per_tick: int = 8) -> dict:
     """Replay `requests` (scenarios) arriving at `arrivals` (s, sorted) through
-    `server`; returns latencies, makespan and aggregate cell-updates/s."""
+    `server`; returns latencies, makespan and aggregate cell-updates/s.  At most
+    `submit_per_tick` arrived requests are submitted between two ticks, so a
+    burst of arrivals does not hold back the device."""
     n = len(requests)
     lat = np.zeros(n)
     results = [None] * n if keep_results else None
     outstanding = {}
+    scratch = {}          # result buffers reused when results are not kept
     i = 0
     t0 = time.perf_counter()
     while i < n or outstanding:
         now = time.perf_counter() - t0
-        while i < n and arrivals[i] <= now:
+        k = 0
+        while i < n and arrivals[i] <= now and k < submit_per_tick:
             outstanding[server.submit(requests[i], nsteps)] = i
             i += 1
+            k += 1
         if not outstanding:
             time.sleep(max(0.0, min(arrivals[i] - now, 0.01)))
             continue
         server.tick()
         for tk in server.finished():
             k = outstanding.pop(tk)
-            U, tf, steps = server.result(tk)
+            shape = (6, requests[k].ny, requests[k].nx)
+            buf = None
+            if not keep_results:
+                buf = scratch.get(shape)
+                if buf is None:
+                    buf = scratch[shape] = np.empty(shape)
+            U, tf, steps = server.result(tk, buf)
             lat[k] = time.perf_counter() - t0 - arrivals[k]
             if keep_results:
                 results[k] = (U, tf, steps)
