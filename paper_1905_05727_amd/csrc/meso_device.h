@@ -208,17 +208,28 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w
     if constexpr (NC == 7) w[6] = Ar<S, FAST>::div(q[6], q[1]);
 }
 
-// Slope limiter (Sec. 3): a backward, b forward difference.
+// Slope limiter (Sec. 3): a backward, b forward difference.  The van Leer
+// division is needed only where a b > 0.  In the FP32 modes a wave in which
+// no lane needs it (a region at rest or a uniform state) skips it; the FP64
+// kernel stays branch-free, which keeps its six independent IEEE divisions
+// interleaved (it is latency bound at 2 waves per SIMD).
 template <class R, bool FAST, int LIM>
 __device__ __forceinline__ R limit(R a, R b) {
     const R ab = a * b;
-    R s;
     if (LIM == 1) {
-        s = (a > R(0)) ? fmin(a, b) : fmax(a, b);
-    } else {
-        s = Ar<R, FAST>::div(ab + ab, a + b);
+        const R s = (a > R(0)) ? fmin(a, b) : fmax(a, b);
+        return (ab > R(0)) ? s : R(0);
     }
-    return (ab > R(0)) ? s : R(0);
+    if constexpr (!FAST) {   // FP64: branch-free (keeps the divisions interleaved)
+        const R v = Ar<R, FAST>::div(ab + ab, a + b);
+        return (ab > R(0)) ? v : R(0);
+    }
+    R s = R(0);
+    if (__builtin_amdgcn_ballot_w64(ab > R(0)) != 0) {
+        const R v = Ar<R, FAST>::div(ab + ab, a + b);
+        s = (ab > R(0)) ? v : R(0);
+    }
+    return s;
 }
 
 // MUSCL reconstruction and Hancock half step in primitive variables.
@@ -310,8 +321,8 @@ __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out
 
 // HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f) and, with
 // NC = 7, the reactant-mass flux.  The star state is evaluated once, for the
-// side the contact moves away from; only faces with S* == 0 exactly evaluate
-// both sides and average.
+// side the contact moves away from; faces with S* == 0 exactly (or NaN)
+// evaluate both sides and average instead.
 template <class R, bool FAST, int NC, int EOS>
 __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR[NC],
                                      R out[NC + 1]) {
@@ -325,23 +336,25 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     const R dR = SR - Rs.un;
     const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
                             L.rho * dL - Rs.rho * dR);
-    const bool useL = Ss > R(0);
-    Side<R, NC> K;
-    K.rho = useL ? L.rho : Rs.rho;
-    K.un = useL ? L.un : Rs.un;
-    K.ut = useL ? L.ut : Rs.ut;
-    K.p = useL ? L.p : Rs.p;
-    K.z = useL ? L.z : Rs.z;
-    K.E = useL ? L.E : Rs.E;
-#pragma unroll
-    for (int c = 0; c < NC - 1; ++c) {
-        K.U[c] = useL ? L.U[c] : Rs.U[c];
-        K.F[c] = useL ? L.F[c] : Rs.F[c];
-    }
     R st[NC + 1];
-    star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
-    if (!(Ss > R(0)) && !(Ss < R(0))) {
-        // contact at rest relative to the face: average of both star branches
+    if (Ss > R(0) || Ss < R(0)) {
+        const bool useL = Ss > R(0);
+        Side<R, NC> K;
+        K.rho = useL ? L.rho : Rs.rho;
+        K.un = useL ? L.un : Rs.un;
+        K.ut = useL ? L.ut : Rs.ut;
+        K.p = useL ? L.p : Rs.p;
+        K.z = useL ? L.z : Rs.z;
+        K.E = useL ? L.E : Rs.E;
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c) {
+            K.U[c] = useL ? L.U[c] : Rs.U[c];
+            K.F[c] = useL ? L.F[c] : Rs.F[c];
+        }
+        star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
+    } else {
+        // contact at rest relative to the face (every face of a region at
+        // rest): average of both star branches
         R a[NC + 1], b[NC + 1];
         star_flux<R, FAST, NC>(L, SL, Ss, a);
         star_flux<R, FAST, NC>(Rs, SR, Ss, b);
