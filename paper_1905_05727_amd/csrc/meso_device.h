@@ -434,6 +434,59 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
     __syncthreads();
 }
 
+// x_row for the batched kernel: idle (uniform per wave) means the wave lies
+// wholly right of the grid's last halo column, so nothing that is stored
+// depends on it; it only takes part in the barriers.
+template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+__device__ __forceinline__ void x_row_skip(const S q[NC], S qo[NC], int t, S lam, R hl,
+                                      const Mix<S> &ms, const Mix<R> &mr,
+                                      R (*sWF)[kThreads], R (*sH)[kThreads], bool idle) {
+    S w[NC], r, rc2;
+    R wr[NC];
+    if (!idle) {
+        cons_to_prim<S, FAST, NC, EOS>(ms, q, w, r, rc2);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            wr[c] = (R)w[c];
+            sWF[c][t] = wr[c];
+        }
+    }
+    __syncthreads();
+    R wl[NC], wh[NC];
+    if (!idle && t >= 1 && t <= kThreads - 2) {
+        R wm[NC], wp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            wm[c] = sWF[c][t - 1];
+            wp[c] = sWF[c][t + 1];
+        }
+        face_states<R, FAST, LIM, NC>(wm, wr, wp, (R)r, (R)rc2, hl, wl, wh);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sH[c][t] = wh[c];
+    }
+    __syncthreads();
+    R f[NC + 1];
+    if (!idle && t >= 2 && t <= kThreads - 2) {
+        R whm[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) whm[c] = sH[c][t - 1];
+        hllc<R, FAST, NC, EOS>(mr, whm, wl, f);
+#pragma unroll
+        for (int c = 0; c < NC + 1; ++c) sWF[c][t] = f[c];
+    }
+    __syncthreads();
+    if (!idle && t >= 2 && t <= kThreads - 3) {
+        R fh[NC + 1];
+#pragma unroll
+        for (int c = 0; c < NC + 1; ++c) fh[c] = sWF[c][t + 1];
+        update_cell<S, R, NC>(q, f, fh, lam, qo);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qo[c] = q[c];
+    }
+    __syncthreads();
+}
+
 // y sweep as a rolling window down one column (registers only).  Rows are
 // pushed in order; after the 5th row the window yields the updated row two
 // behind the one pushed.  Values are in the y frame (normal momentum rho v).
@@ -563,7 +616,8 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // of two sweeps) applies the first half of the reaction stage (NC = 7) to
 // every value it loads, halo cells included.  All threads of the workgroup
 // call it.
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
+template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS,
+          bool SKIP = false>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
                                          R (*sWF)[kThreads], R (*sH)[kThreads]) {
     Control *ctl = d.ctl;
@@ -588,6 +642,9 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     const int col = x0 - kHalo + t;
     const int gcol = map_idx(col, d.nx, d.bc_xlo, d.bc_xhi);
     const bool out_col = (t >= kHalo) && (t < kThreads - kHalo) && (col < d.nx);
+    // SKIP: a wave whose first column lies beyond the grid's last halo column
+    // does no arithmetic (the mostly empty last strip of a small grid)
+    [[maybe_unused]] const bool idle = SKIP && (x0 - kHalo + (t & ~63) >= d.nx + kHalo);
     const int y0 = by * d.seg_h;
     const int y1 = min(y0 + d.seg_h, d.ny);
     const S zlo = (S)d.zlo, zhi = (S)d.zhi, idx = (S)d.idx, idy = (S)d.idy;
@@ -596,6 +653,13 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     int bad = 0;
 
     auto load = [&](int k, S q[NC]) {
+        if constexpr (SKIP) {
+            if (idle) {   // nothing to read; keep the registers defined
+#pragma unroll
+                for (int c = 0; c < NC; ++c) q[c] = S(0);
+                return;
+            }
+        }
         const int gk = map_idx(k, d.ny, d.bc_ylo, d.bc_yhi);
         const long long o = (long long)gk * d.pitch + gcol;
 #pragma unroll
@@ -620,7 +684,11 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             for (int c = 0; c < NC; ++c) q[c] = qn[c];
             if (k + 1 < y1) load(k + 1, qn);
             start(q);
-            x_row<S, R, FAST, LIM, NC, EOS>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
+            if constexpr (SKIP)
+                x_row_skip<S, R, FAST, LIM, NC, EOS>(q, qo, t, lamx, hlx, ms, mr, sWF, sH,
+                                                     idle);
+            else
+                x_row<S, R, FAST, LIM, NC, EOS>(q, qo, t, lamx, hlx, ms, mr, sWF, sH);
             if (out_col) store(k, qo);
         }
     } else {
@@ -637,22 +705,35 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             start(q);
             if (MODE == kXY) {
                 S qs[NC], qy[NC], qo[NC], qu[NC];
-                x_row<S, R, FAST, LIM, NC, EOS>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
+                if constexpr (SKIP)
+                    x_row_skip<S, R, FAST, LIM, NC, EOS>(q, qs, t, lamx, hlx, ms, mr, sWF, sH,
+                                                         idle);
+                else
+                    x_row<S, R, FAST, LIM, NC, EOS>(q, qs, t, lamx, hlx, ms, mr, sWF, sH);
                 to_yframe<S, NC>(qs, qy);
-                if (yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
+                if ((!SKIP || !idle) && yp.push(cnt, qy, qo, lamy, hly, ms, mr)) {
                     to_yframe<S, NC>(qo, qu);
                     if (out_col) store(k - kHalo, qu);
                 }
             } else {
                 S qy[NC], qo[NC], qu[NC];
                 to_yframe<S, NC>(q, qy);
-                const bool got = yp.push(cnt, qy, qo, lamy, hly, ms, mr);
+                // the window yields a row from the 5th push on, in every wave alike
+                bool got;
+                if constexpr (SKIP)
+                    got = idle ? cnt >= 4 : yp.push(cnt, qy, qo, lamy, hly, ms, mr);
+                else
+                    got = yp.push(cnt, qy, qo, lamy, hly, ms, mr);
                 to_yframe<S, NC>(qo, qu);
                 if (MODE == kY) {
                     if (got && out_col) store(k - kHalo, qu);
                 } else if (got) {  // kYX: x sweep of the row just finished in y
                     S qx[NC];
-                    x_row<S, R, FAST, LIM, NC, EOS>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
+                    if constexpr (SKIP)
+                        x_row_skip<S, R, FAST, LIM, NC, EOS>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH,
+                                                             idle);
+                    else
+                        x_row<S, R, FAST, LIM, NC, EOS>(qu, qx, t, lamx, hlx, ms, mr, sWF, sH);
                     if (out_col) store(k - kHalo, qx);
                 }
             }
@@ -673,9 +754,10 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
 // Fused state update of many solves in one launch: workgroup b takes tile
 // tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
 // (x-y order and source copy), read from its control block.  Inert solves
-// only (NC = 6); the liquid is chosen per tile (EOS from the solve's
-// descriptor), so this kernel holds both liquid variants.
-template <class S, class R, bool FAST, int LIM>
+// with the liquid EOS only (the server launches one of these per liquid
+// present); waves beyond a small grid's last halo column skip their
+// arithmetic (SKIP).
+template <class S, class R, bool FAST, int LIM, int EOS>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
                                                                 const int4 *tiles) {
     __shared__ R sWF[7][kThreads];
@@ -684,13 +766,22 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *desc
     const Desc d = descs[tl.x];
     if (d.ctl->skip) return;
     const int par = (int)(d.ctl->step_exec & 1);
-    if (d.eos2 == 1) {
-        if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, 1>(d, tl.y, tl.z, 0, sWF, sH);
-        else run_tile<S, R, FAST, LIM, kYX, true, 6, 1>(d, tl.y, tl.z, 1, sWF, sH);
-    } else {
-        if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, 0>(d, tl.y, tl.z, 0, sWF, sH);
-        else run_tile<S, R, FAST, LIM, kYX, true, 6, 0>(d, tl.y, tl.z, 1, sWF, sH);
-    }
+    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, EOS, true>(d, tl.y, tl.z, 0, sWF, sH);
+    else run_tile<S, R, FAST, LIM, kYX, true, 6, EOS, true>(d, tl.y, tl.z, 1, sWF, sH);
+}
+
+// Host-side launch of the batched kernel for one liquid and limiter.
+template <class S, class R, bool FAST>
+void launch_batched_variants(const Desc *descs, const int4 *tiles, int ntiles, int lim, int eos,
+                             hipStream_t st) {
+    void (*k)(const Desc *, const int4 *);
+    if (lim == 1)
+        k = eos == 1 ? batched_step_kernel<S, R, FAST, 1, 1>
+                     : batched_step_kernel<S, R, FAST, 1, 0>;
+    else
+        k = eos == 1 ? batched_step_kernel<S, R, FAST, 0, 1>
+                     : batched_step_kernel<S, R, FAST, 0, 0>;
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(kThreads), 0, st, descs, tiles);
 }
 
 // Host-side launch of the step kernel variant for one sweep mode (kXY, kYX,

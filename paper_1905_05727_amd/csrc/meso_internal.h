@@ -99,15 +99,16 @@ hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipS
 hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const double *edges,
                             int nbins, double m_ref, double dn, double *bins, hipStream_t st);
 // Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
-// into descs, strip, segment, unused).
+// into descs, strip, segment, unused); every tile of one launch belongs to a
+// solve whose liquid is `eos`.
 hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                               int lim, hipStream_t st);
+                               int lim, int eos, hipStream_t st);
 // The FP32-bulk and FP32 instantiations (meso_kernels_fast.hip).
 hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                             hipStream_t st);
 hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                                    int lim, hipStream_t st);
+                                    int lim, int eos, hipStream_t st);
 // Reactive solves (seven components): FP64 (meso_kernels_react.hip) and the
 // FP32-bulk / FP32 modes (meso_kernels_react_fast.hip).
 hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int final_pass, int src,

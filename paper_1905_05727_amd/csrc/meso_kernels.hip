@@ -412,15 +412,10 @@ hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st) {
 }
 
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                               int lim, hipStream_t st) {
+                               int lim, int eos, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (prec != kP64) return launch_batched_step_fast(descs, tiles, ntiles, prec, lim, st);
-    if (lim == 1)
-        hipLaunchKernelGGL((batched_step_kernel<double, double, false, 1>), dim3(ntiles),
-                           dim3(kThreads), 0, st, descs, tiles);
-    else
-        hipLaunchKernelGGL((batched_step_kernel<double, double, false, 0>), dim3(ntiles),
-                           dim3(kThreads), 0, st, descs, tiles);
+    if (prec != kP64) return launch_batched_step_fast(descs, tiles, ntiles, prec, lim, eos, st);
+    launch_batched_variants<double, double, false>(descs, tiles, ntiles, lim, eos, st);
     return hipGetLastError();
 }
 

@@ -18,21 +18,10 @@ hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int fina
     return hipGetLastError();
 }
 
-template <class S, class R>
-static void batched_fast_t(const Desc *descs, const int4 *tiles, int ntiles, int lim,
-                           hipStream_t st) {
-    if (lim == 1)
-        hipLaunchKernelGGL((batched_step_kernel<S, R, true, 1>), dim3(ntiles), dim3(kThreads), 0,
-                           st, descs, tiles);
-    else
-        hipLaunchKernelGGL((batched_step_kernel<S, R, true, 0>), dim3(ntiles), dim3(kThreads), 0,
-                           st, descs, tiles);
-}
-
 hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                                    int lim, hipStream_t st) {
-    if (prec == kPMix) batched_fast_t<double, float>(descs, tiles, ntiles, lim, st);
-    else batched_fast_t<float, float>(descs, tiles, ntiles, lim, st);
+                                    int lim, int eos, hipStream_t st) {
+    if (prec == kPMix) launch_batched_variants<double, float, true>(descs, tiles, ntiles, lim, eos, st);
+    else launch_batched_variants<float, float, true>(descs, tiles, ntiles, lim, eos, st);
     return hipGetLastError();
 }
 

@@ -140,6 +140,7 @@ struct mf_server {
     bool dirty;
     int n_active;
     int n_tiles;
+    int n_tiles_eos[2];              // tiles of stiffened-gas / Cochran-Chan liquids (in that order)
     int64_t active_cells;
     // uploads of initial states: pinned buffers, filled at submission, free
     // again once their copy to the device has been enqueued
@@ -291,13 +292,18 @@ int32_t rebuild_tables(mf_server *s) {
     std::vector<Desc> descs;
     std::vector<int4> tiles;
     int64_t cells = 0;
-    for (auto &sl : s->slots) {
-        if (!sl.used || sl.draining) continue;
-        const int k = (int)descs.size();
-        descs.push_back(sl.d);
-        for (int by = 0; by < sl.d.nsegs; ++by)
-            for (int bx = 0; bx < sl.d.nstrips; ++bx) tiles.push_back(make_int4(k, bx, by, 0));
-        cells += (int64_t)sl.d.nx * sl.d.ny;
+    // tiles grouped by liquid: one batched launch per equation of state
+    for (int eos = 0; eos < 2; ++eos) {
+        const size_t before = tiles.size();
+        for (auto &sl : s->slots) {
+            if (!sl.used || sl.draining || sl.d.eos2 != eos) continue;
+            const int k = (int)descs.size();
+            descs.push_back(sl.d);
+            for (int by = 0; by < sl.d.nsegs; ++by)
+                for (int bx = 0; bx < sl.d.nstrips; ++bx) tiles.push_back(make_int4(k, bx, by, 0));
+            cells += (int64_t)sl.d.nx * sl.d.ny;
+        }
+        s->n_tiles_eos[eos] = (int)(tiles.size() - before);
     }
     s->n_active = (int)descs.size();
     s->n_tiles = (int)tiles.size();
@@ -500,9 +506,12 @@ int32_t mf_server_tick(mf_server *s, int32_t *active, int32_t *queued) {
             s->ev_pool.push_back(old);
         }
         hipError_t e = meso::launch_batched_dt(s->d_descs, s->n_active, s->st);
-        if (e == hipSuccess)
-            e = meso::launch_batched_step(s->d_descs, s->d_tiles, s->n_tiles, s->cfg.precision,
-                                          s->cfg.limiter, s->st);
+        int first = 0;
+        for (int eos = 0; eos < 2 && e == hipSuccess; ++eos) {
+            e = meso::launch_batched_step(s->d_descs, s->d_tiles + first, s->n_tiles_eos[eos],
+                                          s->cfg.precision, s->cfg.limiter, eos, s->st);
+            first += s->n_tiles_eos[eos];
+        }
         hipEvent_t ev = take_event(s);
         if (!ev) return MF_E_DEVICE;
         if (e == hipSuccess) e = hipEventRecord(ev, s->st);

@@ -56,6 +56,25 @@ def test_alone_equals_in_mix(prec):
         assert np.array_equal(o.U, got[0][0])
 
 
+def test_mixed_liquids_alone_equals_in_mix():
+    """Water and nitromethane requests in one server: each tick runs one
+    batched launch per liquid; every result equals its lone solve."""
+    water = small_requests(3, seed=17, sizes=(64, 100))
+    nm = [S.single_bubble(nx=n, ny=m, dx=1e-6, radius=m / 5, centre=(n * 0.55, m / 2),
+                          shock_x=n * 0.3, liquid="nm", p_shock=7.81e9)
+          for n, m in ((64, 48), (120, 60), (260, 40))]
+    reqs = [water[0], nm[0], water[1], nm[1], nm[2], water[2]]
+    say("case: mixed liquids, 6 requests, 23 steps, fp64")
+    with serve.Server(1 << 29, max_slots=4, precision="fp64") as srv:
+        tks = [srv.submit(sc, 23) for sc in reqs]
+        srv.drain()
+        got = [srv.result(tk) for tk in tks]
+    for sc, (Ub, tb, nb) in zip(reqs, got):
+        U, t, n = serve.solve_alone(sc, 23, precision="fp64")
+        assert nb == n == 23 and tb == t
+        assert np.array_equal(U, Ub)
+
+
 def test_finished_reports_each_ticket_once():
     reqs = small_requests(5, seed=13, sizes=(64, 100))
     say("case: finished tickets, 5 requests")
