@@ -286,8 +286,9 @@ typedef struct {
     int32_t reserved;
 } mf_server_stats;
 
-/* Device bytes one request of this grid needs inside the arena. */
-size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision);
+/* Device bytes one request of this grid and these materials (NULL: an inert
+ * pair) needs inside the arena; 0 for an invalid grid, precision or pair. */
+size_t mf_server_request_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision);
 
 /* Create a server on the current device.  hip_stream: stream for the batched
  * steps (NULL: the server creates its own non-blocking stream); the read-back
@@ -295,12 +296,12 @@ size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision);
  * MF_E_OUT_OF_MEMORY (arena allocation), MF_E_DEVICE. */
 int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_server **out);
 
-/* Queue one solve: grid, materials (gas, liquid; inert only -- a reactive
- * liquid gives MF_E_INVALID_ARG), options (cfl, z_floor; limiter and
- * precision must equal the server's; fused is ignored), host primitive planes
- * (6*nx*ny doubles, copied during the call) and the number of CFL steps to
- * take (>= 1).  *ticket receives the request id.  MF_E_OUT_OF_MEMORY if the
- * request can never fit in the budget. */
+/* Queue one solve: grid, materials (gas, liquid; the liquid may be reactive),
+ * options (cfl, z_floor; limiter and precision must equal the server's; fused
+ * is ignored), host primitive planes (6*nx*ny doubles, 7*nx*ny with lambda
+ * last for a reactive liquid; copied during the call) and the number of CFL
+ * steps to take (>= 1).  *ticket receives the request id.  MF_E_OUT_OF_MEMORY
+ * if the request can never fit in the budget. */
 int32_t mf_server_submit(mf_server *srv, const mf_grid *grid, const mf_material mat[2],
                          const mf_options *opt, const double *prim, int64_t nsteps,
                          uint64_t *ticket);
@@ -321,8 +322,9 @@ int32_t mf_server_poll(mf_server *srv, uint64_t ticket, int32_t *state);
  * serving loop find finished work without polling every outstanding ticket. */
 int32_t mf_server_finished(mf_server *srv, uint64_t *tickets, int32_t capacity, int32_t *count);
 
-/* Copy a finished request's 6 conserved planes (6*nx*ny doubles), its final
- * time and step count, and forget the request.  MF_E_NOT_READY while it runs,
+/* Copy a finished request's conserved planes (6*nx*ny doubles, 7*nx*ny for a
+ * reactive liquid; count must be that size), its final time and step count,
+ * and forget the request.  MF_E_NOT_READY while it runs,
  * MF_E_NONFINITE_STATE if its state became non-physical (the ticket is then
  * released as well).  Until its result is taken, a finished request holds a
  * pinned host buffer of its size. */

@@ -753,34 +753,40 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
 
 // Fused state update of many solves in one launch: workgroup b takes tile
 // tiles[b] = (solve, strip, segment).  Each solve keeps its own step parity
-// (x-y order and source copy), read from its control block.  Inert solves
-// with the liquid EOS only (the server launches one of these per liquid
-// present); waves beyond a small grid's last halo column skip their
-// arithmetic (SKIP).
-template <class S, class R, bool FAST, int LIM, int EOS>
+// (x-y order and source copy), read from its control block.  Every tile of a
+// launch has the same liquid EOS and number of conserved planes NC (the server
+// launches one of these per class present); waves beyond a small grid's last
+// halo column skip their arithmetic (SKIP).
+template <class S, class R, bool FAST, int LIM, int EOS, int NC>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
                                                                 const int4 *tiles) {
-    __shared__ R sWF[7][kThreads];
-    __shared__ R sH[6][kThreads];
+    __shared__ R sWF[NC + 1][kThreads];
+    __shared__ R sH[NC][kThreads];
     const int4 tl = tiles[blockIdx.x];
     const Desc d = descs[tl.x];
     if (d.ctl->skip) return;
     const int par = (int)(d.ctl->step_exec & 1);
-    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, 6, EOS, true>(d, tl.y, tl.z, 0, sWF, sH);
-    else run_tile<S, R, FAST, LIM, kYX, true, 6, EOS, true>(d, tl.y, tl.z, 1, sWF, sH);
+    if (par == 0) run_tile<S, R, FAST, LIM, kXY, true, NC, EOS, true>(d, tl.y, tl.z, 0, sWF, sH);
+    else run_tile<S, R, FAST, LIM, kYX, true, NC, EOS, true>(d, tl.y, tl.z, 1, sWF, sH);
 }
 
-// Host-side launch of the batched kernel for one liquid and limiter.
-template <class S, class R, bool FAST>
+// Host-side launch of the batched kernel for one class of solves: an inert
+// liquid with EoS eos (NC = 6), or the reactive Cochran-Chan liquid (NC = 7).
+template <class S, class R, bool FAST, int NC>
 void launch_batched_variants(const Desc *descs, const int4 *tiles, int ntiles, int lim, int eos,
                              hipStream_t st) {
     void (*k)(const Desc *, const int4 *);
-    if (lim == 1)
-        k = eos == 1 ? batched_step_kernel<S, R, FAST, 1, 1>
-                     : batched_step_kernel<S, R, FAST, 1, 0>;
-    else
-        k = eos == 1 ? batched_step_kernel<S, R, FAST, 0, 1>
-                     : batched_step_kernel<S, R, FAST, 0, 0>;
+    if constexpr (NC == 7) {
+        k = lim == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 7>
+                     : batched_step_kernel<S, R, FAST, 0, 1, 7>;
+    } else {
+        if (lim == 1)
+            k = eos == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 6>
+                         : batched_step_kernel<S, R, FAST, 1, 0, 6>;
+        else
+            k = eos == 1 ? batched_step_kernel<S, R, FAST, 0, 1, 6>
+                         : batched_step_kernel<S, R, FAST, 0, 0, 6>;
+    }
     hipLaunchKernelGGL(k, dim3(ntiles), dim3(kThreads), 0, st, descs, tiles);
 }
 

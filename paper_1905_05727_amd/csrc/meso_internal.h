@@ -100,10 +100,10 @@ hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const d
                             int nbins, double m_ref, double dn, double *bins, hipStream_t st);
 // Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
 // into descs, strip, segment, unused); every tile of one launch belongs to a
-// solve whose liquid is `eos`.
+// solve whose liquid is `eos` and which has `nc` conserved planes (7: reactive).
 hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                               int lim, int eos, hipStream_t st);
+                               int lim, int eos, int nc, hipStream_t st);
 // The FP32-bulk and FP32 instantiations (meso_kernels_fast.hip).
 hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                             hipStream_t st);
@@ -115,5 +115,9 @@ hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int fin
                              hipStream_t st);
 hipError_t launch_step_react_fast(const Desc &d, int prec, int lim, int mode, int final_pass,
                                   int src, hipStream_t st);
+hipError_t launch_batched_step_react(const Desc *descs, const int4 *tiles, int ntiles, int prec,
+                                     int lim, hipStream_t st);
+hipError_t launch_batched_step_react_fast(const Desc *descs, const int4 *tiles, int ntiles,
+                                          int prec, int lim, hipStream_t st);
 
 }  // namespace meso

@@ -412,10 +412,11 @@ hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st) {
 }
 
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                               int lim, int eos, hipStream_t st) {
+                               int lim, int eos, int nc, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
+    if (nc == 7) return launch_batched_step_react(descs, tiles, ntiles, prec, lim, st);
     if (prec != kP64) return launch_batched_step_fast(descs, tiles, ntiles, prec, lim, eos, st);
-    launch_batched_variants<double, double, false>(descs, tiles, ntiles, lim, eos, st);
+    launch_batched_variants<double, double, false, 6>(descs, tiles, ntiles, lim, eos, st);
     return hipGetLastError();
 }
 

@@ -20,8 +20,10 @@ hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int fina
 
 hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
                                     int lim, int eos, hipStream_t st) {
-    if (prec == kPMix) launch_batched_variants<double, float, true>(descs, tiles, ntiles, lim, eos, st);
-    else launch_batched_variants<float, float, true>(descs, tiles, ntiles, lim, eos, st);
+    if (prec == kPMix)
+        launch_batched_variants<double, float, true, 6>(descs, tiles, ntiles, lim, eos, st);
+    else
+        launch_batched_variants<float, float, true, 6>(descs, tiles, ntiles, lim, eos, st);
     return hipGetLastError();
 }
 

@@ -15,4 +15,12 @@ hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int fin
     return hipGetLastError();
 }
 
+hipError_t launch_batched_step_react(const Desc *descs, const int4 *tiles, int ntiles, int prec,
+                                     int lim, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    if (prec != kP64) return launch_batched_step_react_fast(descs, tiles, ntiles, prec, lim, st);
+    launch_batched_variants<double, double, false, 7>(descs, tiles, ntiles, lim, 1, st);
+    return hipGetLastError();
+}
+
 }  // namespace meso

@@ -18,4 +18,13 @@ hipError_t launch_step_react_fast(const Desc &d, int prec, int lim, int mode, in
     return hipGetLastError();
 }
 
+hipError_t launch_batched_step_react_fast(const Desc *descs, const int4 *tiles, int ntiles,
+                                          int prec, int lim, hipStream_t st) {
+    if (prec == kPMix)
+        launch_batched_variants<double, float, true, 7>(descs, tiles, ntiles, lim, 1, st);
+    else
+        launch_batched_variants<float, float, true, 7>(descs, tiles, ntiles, lim, 1, st);
+    return hipGetLastError();
+}
+
 }  // namespace meso

@@ -3,7 +3,7 @@
 //
 // Device memory: one arena of hbm_budget bytes allocated at creation; every
 // admitted solve holds one block of it: control block, two state copies and a
-// dense FP64 read-back area (6 planes).  A first-fit free list with
+// dense FP64 read-back area (6 planes; 7 for a reactive liquid).  A first-fit free list with
 // coalescing manages the blocks, so admission can never exceed the budget.
 //
 // Per tick: finished read-backs are harvested (non-blocking event queries),
@@ -50,7 +50,8 @@ struct Request {
     int up;                       // pinned upload buffer (primitive planes) until admitted
     int64_t nsteps;
     int state;                    // MF_REQ_*
-    int rb;                       // pinned read-back buffer (6 planes) once done
+    int rb;                       // pinned read-back buffer (nc planes + control) once done
+    int nc;                       // conserved planes: 6, or 7 for a reactive liquid
     double t_final;
     int64_t steps_final;
 };
@@ -113,8 +114,8 @@ struct FreeList {                 // first-fit arena allocator with coalescing
     }
 };
 
-size_t readback_bytes(const mf_grid *g) {
-    return meso::round_up((size_t)6 * g->nx * (size_t)g->ny * sizeof(double), meso::kAlign);
+size_t readback_bytes(const mf_grid *g, int nc) {
+    return meso::round_up((size_t)nc * g->nx * (size_t)g->ny * sizeof(double), meso::kAlign);
 }
 
 }  // namespace
@@ -140,7 +141,9 @@ struct mf_server {
     bool dirty;
     int n_active;
     int n_tiles;
-    int n_tiles_eos[2];              // tiles of stiffened-gas / Cochran-Chan liquids (in that order)
+    // tiles per class, in this order: stiffened-gas liquid, inert Cochran-Chan
+    // liquid, reactive Cochran-Chan liquid (one batched launch each)
+    int n_tiles_cls[3];
     int64_t active_cells;
     // uploads of initial states: pinned buffers, filled at submission, free
     // again once their copy to the device has been enqueued
@@ -223,13 +226,13 @@ int32_t pool_pinned(std::vector<Pinned> &pool, std::vector<int> &freel, size_t b
     return MF_OK;
 }
 
-size_t request_bytes(const mf_grid *g, int prec) {
-    return meso::kAlign + 2 * meso::state_bytes(g, prec, 6) + readback_bytes(g);
+size_t request_bytes(const mf_grid *g, int prec, int nc) {
+    return meso::kAlign + 2 * meso::state_bytes(g, prec, nc) + readback_bytes(g, nc);
 }
 
 // Upload and convert a request's initial state into a free slot.
 int32_t admit_one(mf_server *s, Request &r, Slot &sl) {
-    const size_t n = (size_t)r.grid.nx * r.grid.ny * 6;
+    const size_t n = (size_t)r.grid.nx * r.grid.ny * r.nc;
     const size_t bytes = n * sizeof(double);
     if (bytes > s->stage_bytes) {
         if (s->d_stage) {
@@ -265,7 +268,7 @@ int32_t admit(mf_server *s) {
             }
         if (free_slot < 0) return MF_OK;
         Request &r = s->reqs[s->queue.front()];
-        const size_t need = request_bytes(&r.grid, s->cfg.precision);
+        const size_t need = request_bytes(&r.grid, s->cfg.precision, r.nc);
         size_t off = 0;
         if (!s->fl.alloc(need, &off)) return MF_OK;   // wait for memory
         Slot &sl = s->slots[free_slot];
@@ -292,18 +295,20 @@ int32_t rebuild_tables(mf_server *s) {
     std::vector<Desc> descs;
     std::vector<int4> tiles;
     int64_t cells = 0;
-    // tiles grouped by liquid: one batched launch per equation of state
-    for (int eos = 0; eos < 2; ++eos) {
+    // tiles grouped by class (liquid EoS, reaction): one batched launch each
+    for (int cls = 0; cls < 3; ++cls) {
         const size_t before = tiles.size();
         for (auto &sl : s->slots) {
-            if (!sl.used || sl.draining || sl.d.eos2 != eos) continue;
+            if (!sl.used || sl.draining) continue;
+            const int c = sl.d.nc == 7 ? 2 : sl.d.eos2;
+            if (c != cls) continue;
             const int k = (int)descs.size();
             descs.push_back(sl.d);
             for (int by = 0; by < sl.d.nsegs; ++by)
                 for (int bx = 0; bx < sl.d.nstrips; ++bx) tiles.push_back(make_int4(k, bx, by, 0));
             cells += (int64_t)sl.d.nx * sl.d.ny;
         }
-        s->n_tiles_eos[eos] = (int)(tiles.size() - before);
+        s->n_tiles_cls[cls] = (int)(tiles.size() - before);
     }
     s->n_active = (int)descs.size();
     s->n_tiles = (int)tiles.size();
@@ -339,27 +344,30 @@ int32_t rebuild_tables(mf_server *s) {
 int32_t start_drain(mf_server *s, Slot &sl) {
     Request &r = s->reqs[sl.req];
     const size_t n = (size_t)r.grid.nx * r.grid.ny;
-    const size_t bytes = 6 * n * sizeof(double) + sizeof(Control);
+    const int nc = r.nc;
+    const size_t bytes = nc * n * sizeof(double) + sizeof(Control);
     // a free pinned read-back buffer
     int pin = -1;
     int32_t rc = pool_pinned(s->rb_pins, s->rb_free, bytes, &pin);
     if (rc != MF_OK) return rc;
     sl.pin = pin;
     sl.draining = true;
-    double *dense = (double *)(s->arena + sl.off + meso::kAlign + 2 * meso::state_bytes(&r.grid, s->cfg.precision, 6));
+    double *dense = (double *)(s->arena + sl.off + meso::kAlign +
+                               2 * meso::state_bytes(&r.grid, s->cfg.precision, nc));
     const int src = (int)(sl.nsteps & 1);
     hipError_t e = hipSuccess;
-    for (int f = 0; f < 6 && e == hipSuccess; ++f)
-        e = meso::launch_read_field(sl.d, s->cfg.precision, src, f, dense + f * n, s->st);
+    for (int f = 0; f < nc && e == hipSuccess; ++f)
+        e = meso::launch_read_field(sl.d, s->cfg.precision, src, f < 6 ? f : MF_Z2RHO2LAM,
+                                    dense + f * n, s->st);
     hipEvent_t conv = take_event(s);
     if (!conv) return MF_E_DEVICE;
     if (e == hipSuccess) e = hipEventRecord(conv, s->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->rb, conv, 0);
     double *hp = s->rb_pins[pin].p;
     if (e == hipSuccess)
-        e = hipMemcpyAsync(hp, dense, 6 * n * sizeof(double), hipMemcpyDeviceToHost, s->rb);
+        e = hipMemcpyAsync(hp, dense, nc * n * sizeof(double), hipMemcpyDeviceToHost, s->rb);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(hp + 6 * n, sl.d.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->rb);
+        e = hipMemcpyAsync(hp + nc * n, sl.d.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->rb);
     sl.done = take_event(s);
     if (!sl.done) return MF_E_DEVICE;
     if (e == hipSuccess) e = hipEventRecord(sl.done, s->rb);
@@ -379,7 +387,7 @@ int32_t harvest(mf_server *s, bool wait) {
         const size_t n = (size_t)r.grid.nx * r.grid.ny;
         const double *hp = s->rb_pins[sl.pin].p;
         Control c;
-        memcpy(&c, hp + 6 * n, sizeof(Control));
+        memcpy(&c, hp + (size_t)r.nc * n, sizeof(Control));
         r.t_final = c.t;
         r.steps_final = c.step;
         r.state = c.err ? MF_REQ_FAILED : MF_REQ_DONE;
@@ -407,9 +415,10 @@ void count(const mf_server *s, int32_t *active, int32_t *queued) {
 
 extern "C" {
 
-size_t mf_server_request_bytes(const mf_grid *grid, int32_t precision) {
+size_t mf_server_request_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision) {
     if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
-    return request_bytes(grid, precision);
+    if (mat && !meso::valid_materials(mat)) return 0;
+    return request_bytes(grid, precision, meso::planes_of(mat));
 }
 
 int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_server **out) {
@@ -458,13 +467,13 @@ int32_t mf_server_submit(mf_server *s, const mf_grid *grid, const mf_material ma
                          const mf_options *opt, const double *prim, int64_t nsteps,
                          uint64_t *ticket) {
     if (!s || !prim || !ticket || nsteps < 1) return MF_E_INVALID_ARG;
-    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt) ||
-        mat[1].reactive != 0)
+    if (!meso::valid_grid(grid) || !meso::valid_materials(mat) || !meso::valid_scheme(opt))
         return MF_E_INVALID_ARG;
     if (opt->precision != s->cfg.precision || opt->limiter != s->cfg.limiter)
         return MF_E_INVALID_ARG;
     if (grid->nx > 1 << 15 || grid->ny > 1 << 15) return MF_E_INVALID_ARG;
-    if (request_bytes(grid, s->cfg.precision) > s->cfg.hbm_budget) return MF_E_OUT_OF_MEMORY;
+    const int nc = meso::planes_of(mat);
+    if (request_bytes(grid, s->cfg.precision, nc) > s->cfg.hbm_budget) return MF_E_OUT_OF_MEMORY;
     Request r;
     r.id = s->next_id++;
     r.grid = *grid;
@@ -472,13 +481,14 @@ int32_t mf_server_submit(mf_server *s, const mf_grid *grid, const mf_material ma
     r.mat[1] = mat[1];
     r.opt = *opt;
     r.opt.fused = 1;
-    const size_t n = (size_t)grid->nx * grid->ny * 6;
+    const size_t n = (size_t)grid->nx * grid->ny * nc;
     int up = -1;
     const int32_t rc = pool_pinned(s->up_pins, s->up_free, n * sizeof(double), &up);
     if (rc != MF_OK) return rc;
     memcpy(s->up_pins[up].p, prim, n * sizeof(double));
     r.up = up;
     r.rb = -1;
+    r.nc = nc;
     r.nsteps = nsteps;
     r.state = MF_REQ_QUEUED;
     r.t_final = 0.0;
@@ -507,10 +517,11 @@ int32_t mf_server_tick(mf_server *s, int32_t *active, int32_t *queued) {
         }
         hipError_t e = meso::launch_batched_dt(s->d_descs, s->n_active, s->st);
         int first = 0;
-        for (int eos = 0; eos < 2 && e == hipSuccess; ++eos) {
-            e = meso::launch_batched_step(s->d_descs, s->d_tiles + first, s->n_tiles_eos[eos],
-                                          s->cfg.precision, s->cfg.limiter, eos, s->st);
-            first += s->n_tiles_eos[eos];
+        for (int cls = 0; cls < 3 && e == hipSuccess; ++cls) {
+            e = meso::launch_batched_step(s->d_descs, s->d_tiles + first, s->n_tiles_cls[cls],
+                                          s->cfg.precision, s->cfg.limiter, cls == 0 ? 0 : 1,
+                                          cls == 2 ? 7 : 6, s->st);
+            first += s->n_tiles_cls[cls];
         }
         hipEvent_t ev = take_event(s);
         if (!ev) return MF_E_DEVICE;
@@ -567,7 +578,7 @@ int32_t mf_server_result(mf_server *s, uint64_t ticket, double *out_cons, size_t
         s->reqs.erase(it);
         return MF_E_NONFINITE_STATE;
     }
-    const size_t n = (size_t)r.grid.nx * r.grid.ny * 6;
+    const size_t n = (size_t)r.grid.nx * r.grid.ny * r.nc;
     if (!out_cons || count_ != n) return MF_E_INVALID_ARG;
     memcpy(out_cons, s->rb_pins[r.rb].p, n * sizeof(double));
     s->rb_free.push_back(r.rb);

@@ -141,7 +141,8 @@ def load_library():
                                          C.c_double, D]),
         "mf_destroy": (C.c_int32, [P]),
         "mf_status_str": (C.c_char_p, [C.c_int32]),
-        "mf_server_request_bytes": (C.c_size_t, [C.POINTER(Grid), C.c_int32]),
+        "mf_server_request_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Material),
+                                                 C.c_int32]),
         "mf_server_create": (C.c_int32, [C.POINTER(ServerConfig), P, C.POINTER(P)]),
         "mf_server_submit": (C.c_int32, [P, C.POINTER(Grid), C.POINTER(Material),
                                          C.POINTER(Options), D, C.c_int64,

@@ -38,9 +38,9 @@ class Server:
         self._shape = {}
 
     @staticmethod
-    def request_bytes(nx, ny, precision="fp32_fp64acc") -> int:
+    def request_bytes(nx, ny, precision="fp32_fp64acc", mats=None) -> int:
         g = meso.make_grid(nx, ny, 1.0, 1.0)
-        return int(meso.load_library().mf_server_request_bytes(C.byref(g),
+        return int(meso.load_library().mf_server_request_bytes(C.byref(g), mats,
                                                               meso.PRECISION[precision]))
 
     def submit(self, sc, nsteps: int) -> int:
@@ -48,12 +48,14 @@ class Server:
         mats = meso.materials_of(sc)
         opt = meso.Options(sc.cfl, sc.zeps, meso.LIMITER[self.limiter],
                            meso.PRECISION[self.precision], 1, 0)
+        nc = 7 if mats[1].reactive else 6
         prim = np.ascontiguousarray(sc.prim, dtype=np.float64)
+        assert prim.shape == (nc, sc.ny, sc.nx)
         t = C.c_uint64()
         meso._chk("mf_server_submit",
                   self._lib.mf_server_submit(self._h, C.byref(g), mats, C.byref(opt),
                                              meso._dptr(prim), int(nsteps), C.byref(t)))
-        self._shape[t.value] = (sc.ny, sc.nx)
+        self._shape[t.value] = (nc, sc.ny, sc.nx)
         return t.value
 
     def tick(self):
@@ -76,11 +78,11 @@ class Server:
 
     def result(self, ticket: int, out: np.ndarray | None = None):
         """(conserved planes, final time, steps) of a finished request; `out`
-        (C-contiguous float64 of shape (6, ny, nx)) is filled if given."""
-        ny, nx = self._shape.pop(ticket)
+        (C-contiguous float64 of shape (planes, ny, nx)) is filled if given."""
+        shape = self._shape.pop(ticket)
         if out is None:
-            out = np.empty((6, ny, nx), dtype=np.float64)
-        assert out.shape == (6, ny, nx) and out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
+            out = np.empty(shape, dtype=np.float64)
+        assert out.shape == shape and out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
         t = C.c_double()
         n = C.c_int64()
         meso._chk("mf_server_result", self._lib.mf_server_result(self._h, ticket, meso._dptr(out),
@@ -143,7 +145,7 @@ def serve(server: Server, requests, arrivals, nsteps: int, keep_results: bool = 
         server.tick()
         for tk in server.finished():
             k = outstanding.pop(tk)
-            shape = (6, requests[k].ny, requests[k].nx)
+            shape = (requests[k].prim.shape[0], requests[k].ny, requests[k].nx)
             buf = None
             if not keep_results:
                 buf = scratch.get(shape)

@@ -125,3 +125,17 @@ def test_null_handles_are_rejected():
     assert lib.mf_create(None, None, None, None, 0, None, None) == -1
     n = C.c_int32()
     assert lib.mf_server_finished(None, None, 0, C.byref(n)) == -1
+
+
+def test_server_request_bytes():
+    lib = meso.load_library()
+    g = meso.make_grid(200, 100, 1.0, 1.0)
+    inert = lib.mf_server_request_bytes(C.byref(g), None, 1)
+    react = lib.mf_server_request_bytes(C.byref(g), reactive_pair(), 1)
+    pitch = 256
+    st6 = (6 * pitch * 100 * 8 + 255) // 256 * 256
+    st7 = (7 * pitch * 100 * 8 + 255) // 256 * 256
+    rb6 = (6 * 200 * 100 * 8 + 255) // 256 * 256
+    rb7 = (7 * 200 * 100 * 8 + 255) // 256 * 256
+    assert inert == 256 + 2 * st6 + rb6 and react == 256 + 2 * st7 + rb7
+    assert lib.mf_server_request_bytes(C.byref(g), None, 9) == 0

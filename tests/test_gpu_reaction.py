@@ -194,9 +194,20 @@ def test_reactive_regular_array_paper_grid_sampled():
     close_fp64(U1.reshape(7, -1)[:, cells], exp, "reactive regular array sampled")
 
 
-def test_server_rejects_reactive_requests():
-    sc = hot_bubble(64, 64)
-    with serve.Server(1 << 28, max_slots=2, precision="fp64") as srv:
-        with pytest.raises(meso.MesoError) as ei:
-            srv.submit(sc, 5)
-        assert ei.value.status == -1
+def test_reactive_requests_served_alone_equals_in_mix():
+    """Reactive and inert requests in one server (one batched launch per
+    class): each result equals its lone solve bit for bit (FP64)."""
+    reqs = [hot_bubble(64, 48), S.single_bubble(nx=100, ny=50, dx=1e-6, radius=10.0,
+                                                 centre=(55.0, 25.0), shock_x=30.0, liquid="nm",
+                                                 p_shock=7.81e9),
+            hot_bubble(130, 64), hot_bubble(260, 40)]
+    say("case: reactive serving, 4 requests, 31 steps")
+    with serve.Server(1 << 29, max_slots=3, precision="fp64") as srv:
+        tks = [srv.submit(sc, 31) for sc in reqs]
+        srv.drain()
+        got = [srv.result(tk) for tk in tks]
+    for sc, (Ub, tb, nb) in zip(reqs, got):
+        assert Ub.shape[0] == (7 if sc.reactive else 6)
+        U, t, n = serve.solve_alone(sc, 31, precision="fp64")
+        assert nb == n == 31 and tb == t
+        assert np.array_equal(U, Ub)
