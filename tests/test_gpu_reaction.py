@@ -84,6 +84,37 @@ def test_reactive_bubble_fp64_matches_oracle(fused):
     assert np.all(np.abs(lam - ref) <= 1e-10)
 
 
+def test_reactive_resume_and_run_to_time():
+    """Checkpoint (7 conserved planes, time, step) and resume in a new solver
+    give the uninterrupted run bit for bit; run-to-time lands on the end time
+    with the reaction stage applied to the shortened last step."""
+    sc = hot_bubble(130, 64)
+    say("case: reactive resume and run-to-time")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(57)
+        ref = s.read_conserved()
+        t_ref, n_ref, _ = s.time()
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(30)
+        U = s.read_conserved()
+        t, n, _ = s.time()
+    with meso.Solver.from_scenario(sc, precision="fp64") as s2:
+        s2.set_conserved(U)
+        s2.set_time(t, n)
+        s2.run_steps(27)
+        assert np.array_equal(s2.read_conserved(), ref)
+        assert s2.time()[:2] == (t_ref, n_ref)
+    t_end = 0.7 * t_ref
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        k = s.run_to_time(t_end)
+        assert s.time()[0] == t_end
+        U = s.read_conserved()
+    o = oracle_of(sc)
+    no = o.run(10 ** 6, t_end=t_end)
+    assert no == k and o.t == t_end
+    close_fp64(U, o.U, "reactive run to time")
+
+
 @pytest.mark.parametrize("prec", ["fp32_fp64acc", "fp32"])
 def test_reactive_reduced_precision(prec):
     sc = hot_bubble(200, 100)
