@@ -1,7 +1,8 @@
 // meso_device.h -- device code of the two-fluid finite-volume update,
-// included by the two kernel translation units (meso_kernels.hip, built
-// without floating-point contraction for the FP64 mode; meso_kernels_fast.hip,
-// built with contraction for the FP32-bulk and FP32 modes).
+// included by the kernel translation units: meso_kernels.hip and
+// meso_kernels_react.hip (FP64 mode, built without floating-point
+// contraction), meso_kernels_fast.hip and meso_kernels_react_fast.hip
+// (FP32-bulk and FP32 modes, built with contraction).
 //
 // Equations: Eq. (1) (Sec. 2.1) -- partial densities, momentum, total energy,
 // non-conservative advection of the air volume fraction z1, and for a
