@@ -45,10 +45,16 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources with comments and whitespace removed (a
+    comment edit does not invalidate a counter summary of the same code)."""
+    import re
     h = hashlib.sha256()
     for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h",
               "meso_api.hip"):
-        h.update(open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
