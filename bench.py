@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -47,7 +48,6 @@ def log(*a):
 def kernel_source_hash() -> str:
     """Hash of the kernel sources with comments and whitespace removed (a
     comment edit does not invalidate a counter summary of the same code)."""
-    import re
     h = hashlib.sha256()
     for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h",
               "meso_api.hip"):
