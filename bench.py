@@ -55,6 +55,8 @@ def kernel_source_hash() -> str:
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
         h.update("".join(text.split()).encode())
+    # the build flags of the kernels (contraction, scheduler) are part of what was measured
+    h.update(open(os.path.join(ROOT, "paper_1905_05727_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 

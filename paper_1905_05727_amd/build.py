@@ -20,10 +20,15 @@ LIB = os.path.join(HERE, "libmeso.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 
-# (source, floating-point contraction)
-UNITS = [("meso_kernels.hip", "off"), ("meso_kernels_fast.hip", "fast"),
-         ("meso_kernels_react.hip", "off"), ("meso_kernels_react_fast.hip", "fast"),
-         ("meso_api.hip", "off"), ("meso_server.hip", "off")]
+# (source, floating-point contraction, extra flags).  The FP64 kernels are
+# latency bound at 2 waves per SIMD; the backend's ILP-maximising scheduler
+# runs them 2-4 % faster (same instructions, reordered).  The FP32-mode kernels
+# keep the default scheduler, which holds their registers under the 3- and
+# 4-wave occupancy limits.
+UNITS = [("meso_kernels.hip", "off", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
+         ("meso_kernels_fast.hip", "fast", []),
+         ("meso_kernels_react.hip", "off", []), ("meso_kernels_react_fast.hip", "fast", []),
+         ("meso_api.hip", "off", []), ("meso_server.hip", "off", [])]
 
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fno-fast-math",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,9 +41,9 @@ def build(verbose: bool = False) -> str:
     recompiles)."""
     with tempfile.TemporaryDirectory(prefix="meso_build_") as tmp:
         jobs = []
-        for src, contract in UNITS:
+        for src, contract, extra in UNITS:
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
-            cmd = [HIPCC, *COMMON, f"-ffp-contract={contract}", "-c", "-o", obj,
+            cmd = [HIPCC, *COMMON, f"-ffp-contract={contract}", *extra, "-c", "-o", obj,
                    os.path.join(CSRC, src)]
             if verbose:
                 print(" ".join(cmd), flush=True)
