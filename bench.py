@@ -10,7 +10,9 @@ the pointwise stage and the next step's CFL maximum.  Inputs are resident in
 HBM before the timed region starts.
 
 Prints ONE JSON line.  The FP64 mode is the headline `value`; the other modes
-are reported under "modes".
+are reported under "modes", the serving benchmark under "serving", and the
+paper's regular cavity array in water, inert and reacting nitromethane under
+"liquids".
 """
 from __future__ import annotations
 
@@ -49,7 +51,8 @@ def kernel_source_hash() -> str:
     """Hash of the kernel sources with comments and whitespace removed (a
     comment edit does not invalidate a counter summary of the same code)."""
     h = hashlib.sha256()
-    for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip", "meso_internal.h",
+    for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip",
+              "meso_kernels_react.hip", "meso_kernels_react_fast.hip", "meso_internal.h",
               "meso_api.hip"):
         text = open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -178,7 +181,12 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
 
 def cpu_baseline(sc, nsteps):
     import oracle
-    o = oracle.Oracle(oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, cfl=sc.cfl))
+    bc = [{"transmissive": oracle.TRANSMISSIVE, "periodic": oracle.PERIODIC}[b] for b in sc.bc]
+    prob = oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1,
+                          gamma2=sc.gamma2, pinf2=sc.pinf2, cfl=sc.cfl, zeps=sc.zeps,
+                          bc_xlo=bc[0], bc_xhi=bc[1], bc_ylo=bc[2], bc_yhi=bc[3],
+                          eos2=sc.eos2, cc=sc.cc, reactive=int(sc.reactive), rx=sc.rx)
+    o = oracle.Oracle(prob)
     o.set_primitive(sc.prim)
     t0 = time.perf_counter()
     o.run(nsteps)
@@ -187,6 +195,59 @@ def cpu_baseline(sc, nsteps):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"first {nsteps} steps of the full {sc.nx}x{sc.ny} workload, FP64 "
                       f"oracle ({dt:.1f} s)"}
+
+
+# The paper's regular cavity array (Sec. 2.4: d_c = 100 cells, porosity 8 %,
+# spacing 313 cells, 24000 cells long, periodic in y) with each liquid of the
+# build: water (stiffened gas), inert nitromethane (Cochran-Chan, shocked to
+# 7.81 GPa) and reacting nitromethane (7th conserved plane, Arrhenius stage).
+LIQUIDS = (("water", {}),
+           ("nitromethane", {"liquid": "nm", "p_shock": 7.81e9}),
+           ("nitromethane_reactive", {"liquid": "nm", "p_shock": 7.81e9, "reactive": True}))
+
+
+def valu_per_cell_from_profiles(liquid: str, mode: str):
+    """Measured VALU instructions per cell-step of the regular-array kernels
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source and build flags."""
+    p = os.path.join(ROOT, "profiles", "step_kernel_regular_array_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("valu_per_cell", {}).get(f"{liquid}/{mode}")
+
+
+def liquids_bench(modes, steps, warmup, cpu_steps):
+    """Cell-updates/s of the regular cavity array for each liquid and mode,
+    with the HBM fraction (algorithmic bytes), the VALU-issue fraction (counted
+    instructions) and the FP64 oracle on the host cores beside it."""
+    from paper_1905_05727_amd import scenario
+    out = {}
+    for name, kw in LIQUIDS:
+        sc = scenario.regular_array(**kw)
+        N = sc.nx * sc.ny
+        planes = 7 if sc.reactive else 6
+        row = {"grid": [sc.nx, sc.ny], "cavities": sc.meta["ncavities"], "modes": {}}
+        for m in modes:
+            r = run_mode(sc, m, steps, warmup)
+            kms = r["kernel_ms_avg"]
+            nbytes = 2 * planes * (4 if m == "fp32" else 8) * N
+            d = {"value": N * steps / r["s"], "kernel_ms": kms,
+                 "hbm_algorithmic_GBs": nbytes / (kms * 1e-3) / 1e9}
+            d["hbm_frac"] = d["hbm_algorithmic_GBs"] / HBM_PEAK_GBS
+            v = valu_per_cell_from_profiles(name, m)
+            if v is not None:
+                d["valu_per_cell"] = v
+                d["valu_issue_frac"] = v * N / (kms * 1e-3) / (ALU_PEAK_TOPS * 1e12)
+            row["modes"][m] = d
+            log(f"  {name} {m}: {d['value'] / 1e9:.2f} G cell-updates/s, kernel {kms:.3f} ms")
+        if cpu_steps:
+            row["cpu_baseline"] = cpu_baseline(sc, cpu_steps)
+            log(f"  {name} oracle: {row['cpu_baseline']['value'] / 1e6:.1f} M cell-updates/s")
+        out[name] = row
+    return out
 
 
 def main():
@@ -201,6 +262,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--liquid-steps", type=int, default=200,
+                    help="timed steps of each regular-array run (0: skip that section)")
+    ap.add_argument("--liquids-only", action="store_true",
+                    help="only the regular-array section (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs one domain on one GPU; multi-GPU runs are not "
@@ -213,11 +278,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
 
+    modes = [m for m in args.modes.split(",") if m]
+    if args.liquids_only:
+        print(json.dumps({"liquids": liquids_bench(modes, args.liquid_steps, args.warmup, 0)}),
+              flush=True)
+        return
+
     t = time.perf_counter()
     sc = scenario.roofline_8192(n=args.n)
     log(f"scenario {sc.name} {sc.nx}x{sc.ny}: {sc.meta['nbubbles']} bubbles, porosity "
         f"{sc.meta['porosity']:.3f} ({time.perf_counter() - t:.1f} s)")
-    modes = [m for m in args.modes.split(",") if m]
     N = sc.nx * sc.ny
     res = {}
     for m in modes:
@@ -285,6 +355,10 @@ def main():
     }
     if not args.no_serving:
         line["serving"] = serving_bench(args.serving_requests, args.serving_steps)
+    if args.liquid_steps:
+        log(f"regular cavity array: {args.liquid_steps} steps per liquid and mode")
+        line["liquids"] = liquids_bench(modes, args.liquid_steps, args.warmup,
+                                        0 if args.no_cpu_baseline else 4)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)

@@ -743,9 +743,15 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
 }
 
+// Extra attributes of the two state-update kernels, set by a translation unit
+// before it includes this header (empty: the compiler's own occupancy choice).
+#ifndef MESO_STEP_ATTR
+#define MESO_STEP_ATTR
+#endif
+
 // State update of one solve: grid (strips, segments).
 template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
-__global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
+__global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void step_kernel(Desc d, int src_idx) {
     __shared__ R sWF[NC + 1][kThreads];
     __shared__ R sH[NC][kThreads];
     if (d.ctl->skip) return;
@@ -759,8 +765,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Desc d, int src_idx) {
 // launches one of these per class present); waves beyond a small grid's last
 // halo column skip their arithmetic (SKIP).
 template <class S, class R, bool FAST, int LIM, int EOS, int NC>
-__global__ __launch_bounds__(kThreads) void batched_step_kernel(const Desc *descs,
-                                                                const int4 *tiles) {
+__global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void batched_step_kernel(const Desc *descs,
+                                                                               const int4 *tiles) {
     __shared__ R sWF[NC + 1][kThreads];
     __shared__ R sH[NC][kThreads];
     const int4 tl = tiles[blockIdx.x];

@@ -2,7 +2,13 @@
 // components: the reactant mass z2 rho2 lambda is advected with the flow and
 // reacts in the pointwise stage), FP64 mode.  Built without floating-point
 // contraction, like the inert FP64 kernels.
+//
+// The seventh component's y-pipeline registers push the fused kernel to 276
+// VGPRs, one wave per SIMD; it is compiled for two waves instead (256 VGPRs,
+// 18 spilled to scratch), which hides more of the FP64 latency than the
+// spills cost.
 
+#define MESO_STEP_ATTR __attribute__((amdgpu_waves_per_eu(2)))
 #include "meso_device.h"
 
 namespace meso {
