@@ -236,7 +236,10 @@ int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches);
 
 /* Kernel launch geometry of the state-update kernel for this solver:
  * workgroups, threads per workgroup, and the number of cells one workgroup
- * writes (strip width x segment height). */
+ * writes (strip width x segment height).  The segment height is chosen at
+ * creation from the grid and the device's compute units (short segments for
+ * small grids, so that every compute unit gets several workgroups); the
+ * environment variable MESO_SEG_H (>= 1) fixes it.  No result depends on it. */
 int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int32_t *tile_w,
                        int32_t *tile_h);
 
@@ -244,8 +247,12 @@ int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int3
  * Continuous-batching server: many independent solves of different grid
  * sizes share one device.  Each admitted solve holds a slot and a block of a
  * fixed device arena (its state copies, control block and a read-back area);
- * every tick advances all admitted solves by one CFL step with ONE batched
- * state-update launch over a table of (solve, strip, segment) tiles.  Solves
+ * every tick advances all admitted solves by one CFL step with one batched
+ * state-update launch per class of liquid (stiffened gas, inert and reactive
+ * Cochran-Chan) over a table of (solve, strip, segment) tiles.  The rows per
+ * segment follow the load: few solves get short segments (more workgroups in
+ * flight), a full device taller ones (less halo work); the environment
+ * variable MESO_SERVE_SEG_H (>= 1) fixes the height.  Solves
  * that finish are read back on a second stream while the others keep running;
  * their slot and memory are then reused by queued requests (first come, first
  * served).  Each solve's arithmetic is exactly that of a lone mf_solver with

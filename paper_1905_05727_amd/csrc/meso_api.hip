@@ -76,19 +76,46 @@ size_t state_bytes(const mf_grid *g, int prec, int nc) {
     return round_up((size_t)nc * pitch_of(g->nx) * (size_t)g->ny * es, kAlign);
 }
 
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+int seg_h_model(const int *nstrips, const int *ny, int n, int cus) {
+    // Time per cell of a launch with h-row segments, fitted to kernel times
+    // measured on MI355X over grids from 1000 x 4 to 8192 x 8192 in all three
+    // precisions: (h + 4) / h, since a segment also sweeps its 4 halo rows in
+    // x, times 1 + 1.3 CUs / workgroups, the imbalance of few workgroups per
+    // compute unit at the end of the launch.  Ties go to the taller segment.
+    static const int kCand[] = {64, 48, 40, 32, 24, 20, 16, 12, 8, 6, 4, 2, 1};
+    if (cus <= 0) cus = 256;
+    int best = kCand[0];
+    double best_t = -1.0;
+    for (const int h : kCand) {
+        double wgs = 0.0;
+        for (int i = 0; i < n; ++i) wgs += (double)nstrips[i] * ((ny[i] + h - 1) / h);
+        if (wgs <= 0.0) continue;
+        const double t = (h + 4.0) / h * (1.0 + 1.3 * cus / wgs);
+        if (best_t < 0.0 || t < best_t) {
+            best_t = t;
+            best = h;
+        }
+    }
+    return best;
+}
+
 int choose_seg_h(int nstrips, int ny) {
     const char *env = getenv("MESO_SEG_H");
     if (env) {
         const int v = atoi(env);
         if (v >= 1) return v;
     }
-    // 64-row segments: measured fastest on 8192^2 in every precision (more
-    // workgroups shorten the tail of the last round of the launch; the two
-    // halo rows per side cost 6 % extra x-sweep work); shorter segments for
-    // grids that would otherwise launch fewer than 512 workgroups.
-    int h = 64;
-    while (h > 16 && (long long)nstrips * ((ny + h - 1) / h) < 512) h >>= 1;
-    return h;
+    return seg_h_model(&nstrips, &ny, 1, device_cus());
 }
 
 void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,

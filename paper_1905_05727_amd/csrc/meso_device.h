@@ -777,23 +777,26 @@ __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void batched_step_kernel(c
     else run_tile<S, R, FAST, LIM, kYX, true, NC, EOS, true>(d, tl.y, tl.z, 1, sWF, sH);
 }
 
-// Host-side launch of the batched kernel for one class of solves: an inert
-// liquid with EoS eos (NC = 6), or the reactive Cochran-Chan liquid (NC = 7).
+// The batched kernel for one class of solves: an inert liquid with EoS eos
+// (NC = 6), or the reactive Cochran-Chan liquid (NC = 7).
+template <class S, class R, bool FAST, int NC>
+auto batched_variant(int lim, int eos) -> void (*)(const Desc *, const int4 *) {
+    if constexpr (NC == 7) {
+        return lim == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 7>
+                        : batched_step_kernel<S, R, FAST, 0, 1, 7>;
+    } else {
+        if (lim == 1)
+            return eos == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 6>
+                            : batched_step_kernel<S, R, FAST, 1, 0, 6>;
+        return eos == 1 ? batched_step_kernel<S, R, FAST, 0, 1, 6>
+                        : batched_step_kernel<S, R, FAST, 0, 0, 6>;
+    }
+}
+
 template <class S, class R, bool FAST, int NC>
 void launch_batched_variants(const Desc *descs, const int4 *tiles, int ntiles, int lim, int eos,
                              hipStream_t st) {
-    void (*k)(const Desc *, const int4 *);
-    if constexpr (NC == 7) {
-        k = lim == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 7>
-                     : batched_step_kernel<S, R, FAST, 0, 1, 7>;
-    } else {
-        if (lim == 1)
-            k = eos == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 6>
-                         : batched_step_kernel<S, R, FAST, 1, 0, 6>;
-        else
-            k = eos == 1 ? batched_step_kernel<S, R, FAST, 0, 1, 6>
-                         : batched_step_kernel<S, R, FAST, 0, 0, 6>;
-    }
+    void (*k)(const Desc *, const int4 *) = batched_variant<S, R, FAST, NC>(lim, eos);
     hipLaunchKernelGGL(k, dim3(ntiles), dim3(kThreads), 0, st, descs, tiles);
 }
 

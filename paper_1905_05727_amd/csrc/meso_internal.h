@@ -72,7 +72,12 @@ int planes_of(const mf_material *mat);
 bool valid_scheme(const mf_options *opt);
 // bytes of one pitched state copy (nc planes), 256-byte rounded
 size_t state_bytes(const mf_grid *g, int prec, int nc);
+// Rows per workgroup segment: for one grid (MESO_SEG_H >= 1 in the
+// environment fixes it), and for one launch over n grids of nstrips[i] strips
+// and ny[i] rows on a device of `cus` compute units (0: 256).
 int choose_seg_h(int nstrips, int ny);
+int seg_h_model(const int *nstrips, const int *ny, int n, int cus);
+int device_cus();
 // Fill a descriptor for a solve whose workspace (control block + two state
 // copies) starts at base.
 void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,

@@ -26,6 +26,7 @@
 #include "meso_internal.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -40,7 +41,9 @@ using meso::Desc;
 
 namespace {
 
-constexpr int kServerSegH = 32;   // rows per workgroup segment for served solves
+// Rows per workgroup segment of a served solve at admission; the tile tables
+// then choose the height per class of solves (class_seg_h).
+constexpr int kServerSegH = 32;
 
 struct Request {
     uint64_t id;
@@ -144,6 +147,7 @@ struct mf_server {
     // tiles per class, in this order: stiffened-gas liquid, inert Cochran-Chan
     // liquid, reactive Cochran-Chan liquid (one batched launch each)
     int n_tiles_cls[3];
+    int n_cu;                     // compute units of the device (0: unknown)
     int64_t active_cells;
     // uploads of initial states: pinned buffers, filled at submission, free
     // again once their copy to the device has been enqueued
@@ -290,18 +294,47 @@ int32_t admit(mf_server *s) {
     return MF_OK;
 }
 
+// Rows per segment for the tiles of one class of solves: the same model as a
+// lone solve's, over all the class's grids (few solves get short segments and
+// more workgroups in flight, a full device taller ones and less halo work).
+// No stored value depends on the height.  MESO_SERVE_SEG_H (>= 1) fixes it.
+int class_seg_h(mf_server *s, const std::vector<Slot *> &members) {
+    if (const char *env = getenv("MESO_SERVE_SEG_H")) {
+        const int v = atoi(env);
+        if (v >= 1) return v;
+    }
+    std::vector<int> strips, rows;
+    for (const Slot *sl : members) {
+        strips.push_back(sl->d.nstrips);
+        rows.push_back(sl->d.ny);
+    }
+    return meso::seg_h_model(strips.data(), rows.data(), (int)members.size(), s->n_cu);
+}
+
 // Rebuild the descriptor and tile tables of the advancing solves.
 int32_t rebuild_tables(mf_server *s) {
     std::vector<Desc> descs;
     std::vector<int4> tiles;
     int64_t cells = 0;
     // tiles grouped by class (liquid EoS, reaction): one batched launch each
+    std::vector<Slot *> members;
     for (int cls = 0; cls < 3; ++cls) {
         const size_t before = tiles.size();
+        members.clear();
         for (auto &sl : s->slots) {
             if (!sl.used || sl.draining) continue;
             const int c = sl.d.nc == 7 ? 2 : sl.d.eos2;
-            if (c != cls) continue;
+            if (c == cls) members.push_back(&sl);
+        }
+        if (members.empty()) {
+            s->n_tiles_cls[cls] = 0;
+            continue;
+        }
+        const int h = class_seg_h(s, members);
+        for (Slot *psl : members) {
+            Slot &sl = *psl;
+            sl.d.seg_h = h;
+            sl.d.nsegs = (sl.d.ny + h - 1) / h;
             const int k = (int)descs.size();
             descs.push_back(sl.d);
             for (int by = 0; by < sl.d.nsegs; ++by)
@@ -450,6 +483,7 @@ int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_serve
         delete s;
         return e == hipErrorOutOfMemory ? MF_E_OUT_OF_MEMORY : MF_E_DEVICE;
     }
+    s->n_cu = meso::device_cus();
     s->fl.init(s->cfg.hbm_budget);
     s->slots.assign(cfg->max_slots, Slot());
     for (auto &sl : s->slots) sl.used = false;
