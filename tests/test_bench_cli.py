@@ -1,0 +1,65 @@
+"""bench.py on the CPU: the multi-GPU refusal, the oracle baseline leg on a
+small grid, and the comment-insensitive source hash that ties committed
+counter summaries to the kernels they were taken on."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1905_05727_amd import scenario as S  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_cpu_baseline_leg_on_a_small_grid():
+    sc = S.single_bubble(nx=96, ny=48, radius=8.0, centre=(50.0, 24.0), shock_x=30.0)
+    out = bench.cpu_baseline(sc, 3)
+    assert out["kind"] == "oracle" and out["unit"] == "cell-updates/s"
+    assert out["value"] > 0 and out["cores"] >= 1
+    assert "96x48" in out["sample"]
+
+
+def test_cpu_baseline_leg_for_each_liquid():
+    # the regular-array section times the oracle per liquid with the
+    # scenario's own materials and boundaries; a cropped copy keeps it short
+    for name, kw in bench.LIQUIDS:
+        sc = S.regular_array(length=700, strip=100, **kw)
+        out = bench.cpu_baseline(sc, 1)
+        assert out["value"] > 0, name
+        assert sc.prim.shape[0] == (7 if kw.get("reactive") else 6)
+
+
+def test_source_hash_ignores_comments_and_whitespace(tmp_path, monkeypatch):
+    src = os.path.join(ROOT, "paper_1905_05727_amd", "csrc")
+    h0 = bench.kernel_source_hash()
+    fake = tmp_path / "paper_1905_05727_amd"
+    (fake / "csrc").mkdir(parents=True)
+    for f in os.listdir(src):
+        if f.endswith((".h", ".hip")):
+            text = open(os.path.join(src, f)).read()
+            if f == "meso_device.h":
+                text = "// a new comment\n/* and a block\n comment */\n" + text.replace(";", " ;")
+            (fake / "csrc" / f).write_text(text)
+    (fake / "build.py").write_bytes(open(os.path.join(ROOT, "paper_1905_05727_amd",
+                                                      "build.py"), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_source_hash() == h0
+    (fake / "csrc" / "meso_device.h").write_text(
+        (fake / "csrc" / "meso_device.h").read_text().replace("kHalo", "kHalo2"))
+    assert bench.kernel_source_hash() != h0
+
+
+def test_bytes_per_cell_and_peaks():
+    assert bench.BYTES_PER_CELL == {"fp64": 96, "fp32_fp64acc": 96, "fp32": 48}
+    assert abs(bench.ALU_PEAK_TOPS - 39.3216) < 1e-9
+    assert np.isclose(bench.HBM_PEAK_GBS, 8000.0)
