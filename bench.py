@@ -76,7 +76,29 @@ def traffic_from_profiles(mode: str):
     return None if m is None else m.get("hbm_bytes_per_launch")
 
 
-def run_mode(sc, prec, steps, warmup, ref=None):
+# Diagnostics of Sec. 4 timed on the state a mode leaves: transverse averages,
+# domain integrals (both from one pass over the columns) and the mass-weighted
+# log-binned PDFs of pressure and density (400 bins, as in the paper's figures).
+DIAGNOSTICS = (("y_averages", lambda o: o.y_averages()),
+               ("integrals", lambda o: o.integrals()),
+               ("pdf_p", lambda o: o.log_histogram(9, 4.0, 0.0125, 400, 1.0)),       # p
+               ("pdf_rho", lambda o: o.log_histogram(6, -1.0, 0.01, 400, 1.0)))      # rho
+
+
+def time_diagnostics(obj, reps: int):
+    """Wall-clock ms per call of each diagnostic (every call returns its result
+    to the host, so it includes the launch, the synchronisation and the copy)."""
+    out = {}
+    for name, f in DIAGNOSTICS:
+        f(obj)
+        t = time.perf_counter()
+        for _ in range(reps):
+            f(obj)
+        out[name] = 1e3 * (time.perf_counter() - t) / reps
+    return out
+
+
+def run_mode(sc, prec, steps, warmup, ref=None, diagnostics=False):
     import torch
     from paper_1905_05727_amd import meso
     s = meso.Solver.from_scenario(sc, precision=prec)
@@ -95,6 +117,8 @@ def run_mode(sc, prec, steps, warmup, ref=None):
     out = {"s": t1 - t0, "kernel_ms_avg": kms / max(launches, 1), "launches": launches,
            "t_sim": t_sim, "step": nstep, "launch": info}
     out["fields"] = {k: s.read_field(k) for k in ("rho", "p")}
+    if diagnostics:
+        out["diagnostics_ms"] = time_diagnostics(s, 5)
     s.close()
     torch.cuda.empty_cache()
     return out
@@ -179,15 +203,35 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
     return out
 
 
-def cpu_baseline(sc, nsteps):
+def oracle_of(sc, rows=None):
+    """The FP64 oracle on the scenario's initial state (its first `rows` rows
+    if given)."""
     import oracle
+    ny = sc.ny if rows is None else rows
     bc = [{"transmissive": oracle.TRANSMISSIVE, "periodic": oracle.PERIODIC}[b] for b in sc.bc]
-    prob = oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1,
+    prob = oracle.Problem(sc.nx, ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1,
                           gamma2=sc.gamma2, pinf2=sc.pinf2, cfl=sc.cfl, zeps=sc.zeps,
                           bc_xlo=bc[0], bc_xhi=bc[1], bc_ylo=bc[2], bc_yhi=bc[3],
                           eos2=sc.eos2, cc=sc.cc, reactive=int(sc.reactive), rx=sc.rx)
     o = oracle.Oracle(prob)
-    o.set_primitive(sc.prim)
+    o.set_primitive(sc.prim[:, :ny, :])
+    return o
+
+
+def oracle_diagnostics(sc, rows):
+    """The oracle's diagnostics on the first `rows` rows of the initial state,
+    per call, scaled to the full grid (they are linear in the cell count)."""
+    import oracle
+    o = oracle_of(sc, rows)
+    ms = time_diagnostics(o, 1)
+    scale = sc.ny / rows
+    return {"ms": {k: v * scale for k, v in ms.items()}, "cores": oracle.num_threads(),
+            "sample": f"{sc.nx}x{rows} crop of the initial state, scaled x{scale:g}"}
+
+
+def cpu_baseline(sc, nsteps):
+    import oracle
+    o = oracle_of(sc)
     t0 = time.perf_counter()
     o.run(nsteps)
     dt = time.perf_counter() - t0
@@ -292,7 +336,7 @@ def main():
     res = {}
     for m in modes:
         log(f"mode {m}: warmup {args.warmup}, timing {args.steps} steps")
-        res[m] = run_mode(sc, m, args.steps, args.warmup)
+        res[m] = run_mode(sc, m, args.steps, args.warmup, diagnostics=(m == "fp64"))
         r = res[m]
         log(f"  {N * args.steps / r['s'] / 1e9:.2f} G cell-updates/s, kernel "
             f"{r['kernel_ms_avg']:.3f} ms/launch, t_sim {r['t_sim']:.3e}")
@@ -362,6 +406,17 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+    if "fp64" in res:
+        # each diagnostic reads the whole FP64 state once (6 planes x 8 B per cell)
+        nbytes = 48 * N
+        g = res["fp64"]["diagnostics_ms"]
+        line["diagnostics"] = {
+            "state": "FP64 roofline field after the timed steps", "bytes_read": nbytes,
+            "gpu_ms": g, "gpu_GBs": {k: nbytes / (v * 1e-3) / 1e9 for k, v in g.items()},
+            "gpu_hbm_frac": {k: nbytes / (v * 1e-3) / 1e9 / HBM_PEAK_GBS for k, v in g.items()},
+            "oracle": (None if args.no_cpu_baseline
+                       else oracle_diagnostics(sc, min(sc.ny, 1024)))}
+        log("diagnostics (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in g.items()))
     print(json.dumps(line), flush=True)
 
 

@@ -243,43 +243,72 @@ __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
 // results do not depend on the launch geometry.
 
 // One thread per column: out[0..2][i] = pbar, rhobar, density-weighted ubar;
-// out[3+c][i] = sum over the column of conserved component c.
-template <class S>
-__global__ void column_kernel(Desc d, int src_idx, double *out) {
+// out[3+c][i] = sum over the column of conserved component c.  One wave per
+// workgroup spreads the columns over as many compute units as possible; the
+// loads of kColRows rows are issued before their sums, which still run one
+// row after the other in increasing j.
+constexpr int kColRows = 16;
+
+template <class S, int NC>
+__global__ __launch_bounds__(64) void column_kernel(Desc d, int src_idx, double *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.nx) return;
     const S *src = (const S *)d.buf[src_idx];
     const Mix<double> m = mix_of<double>(d);
-    const int nc = d.nc;
     double sp = 0.0, sr = 0.0, sm = 0.0, sc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < d.ny; ++j) {
+    auto load = [&](int j, double q[7]) {
         const long long o = (long long)j * d.pitch + i;
-        double q[7], w[6], r, rc2;
-        q[6] = 0.0;
-        for (int c = 0; c < nc; ++c) q[c] = (double)src[c * d.plane + o];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = (double)src[c * d.plane + o];
+        if constexpr (NC == 6) q[6] = 0.0;
+    };
+    auto add = [&](const double q[7]) {
+        double w[6], r, rc2;
         cons_to_prim<double, false, 6>(m, q, w, r, rc2);
         sp = sp + w[4];
         sr = sr + (q[0] + q[1]);
         sm = sm + q[2];
 #pragma unroll
         for (int c = 0; c < 7; ++c) sc[c] = sc[c] + q[c];
+    };
+    int j = 0;
+    for (; j + kColRows <= d.ny; j += kColRows) {
+        double q[kColRows][7];
+#pragma unroll
+        for (int u = 0; u < kColRows; ++u) load(j + u, q[u]);
+#pragma unroll
+        for (int u = 0; u < kColRows; ++u) add(q[u]);
+    }
+    for (; j < d.ny; ++j) {
+        double q[7];
+        load(j, q);
+        add(q);
     }
     const long long n = d.nx;
     out[i] = sp / (double)d.ny;
     out[n + i] = sr / (double)d.ny;
     out[2 * n + i] = sm / sr;
-    for (int c = 0; c < nc; ++c) out[(3 + c) * n + i] = sc[c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[(3 + c) * n + i] = sc[c];
 }
 
-// Domain integrals from the column sums (one thread, increasing i).
+// Domain integrals from the column sums: thread c sums component c's column
+// sums in increasing i (loads issued kColRows ahead of the sums).
 __global__ void integrals_kernel(int nx, int nc, double area, const double *cols, double *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int c = 0; c < nc; ++c) {
-        double tot = 0.0;
-        const double *s = cols + (long long)(3 + c) * nx;
-        for (int i = 0; i < nx; ++i) tot = tot + s[i];
-        out[c] = tot * area;
+    const int c = threadIdx.x;
+    if (blockIdx.x != 0 || c >= nc) return;
+    const double *s = cols + (long long)(3 + c) * nx;
+    double tot = 0.0;
+    int i = 0;
+    for (; i + kColRows <= nx; i += kColRows) {
+        double v[kColRows];
+#pragma unroll
+        for (int u = 0; u < kColRows; ++u) v[u] = s[i + u];
+#pragma unroll
+        for (int u = 0; u < kColRows; ++u) tot = tot + v[u];
     }
+    for (; i < nx; ++i) tot = tot + s[i];
+    out[c] = tot * area;
 }
 
 constexpr int kMaxBins = 1024;
@@ -434,11 +463,11 @@ hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double
 
 
 hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStream_t st) {
-    const int g = (d.nx + 255) / 256;
-    if (prec == kP32)
-        hipLaunchKernelGGL(column_kernel<float>, dim3(g), dim3(256), 0, st, d, src, out);
-    else
-        hipLaunchKernelGGL(column_kernel<double>, dim3(g), dim3(256), 0, st, d, src, out);
+    const int g = (d.nx + 63) / 64;
+    void (*k)(Desc, int, double *);
+    if (prec == kP32) k = d.nc == 7 ? column_kernel<float, 7> : column_kernel<float, 6>;
+    else k = d.nc == 7 ? column_kernel<double, 7> : column_kernel<double, 6>;
+    hipLaunchKernelGGL(k, dim3(g), dim3(64), 0, st, d, src, out);
     return hipGetLastError();
 }
 

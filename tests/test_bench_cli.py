@@ -35,6 +35,8 @@ def test_cpu_baseline_leg_for_each_liquid():
     for name, kw in bench.LIQUIDS:
         sc = S.regular_array(length=700, strip=100, **kw)
         out = bench.cpu_baseline(sc, 1)
+        d = bench.oracle_diagnostics(sc, 64)
+        assert set(d["ms"]) == {"y_averages", "integrals", "pdf_p", "pdf_rho"}
         assert out["value"] > 0, name
         assert sc.prim.shape[0] == (7 if kw.get("reactive") else 6)
 
