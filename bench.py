@@ -63,16 +63,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(mode: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def counters_from_profiles(mode: str):
+    """Mean counters per launch of the step kernel from the committed rocprofv3
+    summary of the roofline field, if it was taken on the current kernel source
+    and build flags."""
     p = os.path.join(ROOT, "profiles", "step_kernel_roofline_8192_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    m = d.get("modes", {}).get(mode)
+    return d.get("modes", {}).get(mode)
+
+
+def traffic_from_profiles(mode: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled by a plain copy)."""
+    m = counters_from_profiles(mode)
     return None if m is None else m.get("hbm_bytes_per_launch")
 
 
@@ -355,6 +361,13 @@ def main():
         if tb is not None:      # counted HBM bytes of the same kernel / its time here
             d["hbm_measured_GBs"] = tb / (r["kernel_ms_avg"] * 1e-3) / 1e9
             d["hbm_measured_frac"] = d["hbm_measured_GBs"] / HBM_PEAK_GBS
+        cm = counters_from_profiles(m)
+        if cm is not None and "SQ_INSTS_VALU" in cm:
+            # counted VALU instructions (one per wave, 64 lanes) of the same kernel / its time
+            # here, against the 4-cycle issue peak of 39.3 T lane-instructions/s
+            d["valu_per_cell"] = cm["SQ_INSTS_VALU"] * 64 / N
+            d["valu_issue_frac"] = (cm["SQ_INSTS_VALU"] * 64 / (r["kernel_ms_avg"] * 1e-3)
+                                    / (ALU_PEAK_TOPS * 1e12))
         if ref is not None and m != "fp64":
             for k in ("rho", "p"):
                 d[f"rel_l1_{k}_vs_fp64"] = float(np.abs(r["fields"][k] - ref["fields"][k]).sum()
@@ -391,6 +404,8 @@ def main():
                      "traffic": traffic_from_profiles(head),
                      "kernel": "step_kernel (fused x/y sweep)",
                      "ops_per_cell": OPS_PER_CELL,
+                     "valu_issue": {"instr_per_cell": h.get("valu_per_cell"),
+                                    "frac": h.get("valu_issue_frac")},
                      "hbm": {"achieved_GBs": h["hbm_algorithmic_GBs"], "peak_GBs": HBM_PEAK_GBS,
                              "frac": h["hbm_frac"], "bytes_per_cell": BYTES_PER_CELL[head],
                              "measured_GBs": h.get("hbm_measured_GBs"),
