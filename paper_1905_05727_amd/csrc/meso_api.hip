@@ -89,18 +89,24 @@ int device_cus() {
 int seg_h_model(const int *nstrips, const int *ny, int n, int cus) {
     // Time per cell of a launch with h-row segments, fitted to kernel times
     // measured on MI355X over grids from 1000 x 4 to 8192 x 8192 in all three
-    // precisions: (h + 4) / h, since a segment also sweeps its 4 halo rows in
-    // x, times 1 + 1.3 CUs / workgroups, the imbalance of few workgroups per
-    // compute unit at the end of the launch.  Ties go to the taller segment.
+    // precisions: the rows swept per row of output (every segment also sweeps
+    // its 4 halo rows in x), times 1 + 1.45 CUs / workgroups, the imbalance of
+    // few workgroups per compute unit at the end of the launch.  Ties go to
+    // the taller segment.
     static const int kCand[] = {64, 48, 40, 32, 24, 20, 16, 12, 8, 6, 4, 2, 1};
     if (cus <= 0) cus = 256;
     int best = kCand[0];
     double best_t = -1.0;
     for (const int h : kCand) {
-        double wgs = 0.0;
-        for (int i = 0; i < n; ++i) wgs += (double)nstrips[i] * ((ny[i] + h - 1) / h);
+        double wgs = 0.0, rows = 0.0, swept = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const int segs = (ny[i] + h - 1) / h;
+            wgs += (double)nstrips[i] * segs;
+            rows += (double)nstrips[i] * ny[i];
+            swept += (double)nstrips[i] * (ny[i] + 4.0 * segs);
+        }
         if (wgs <= 0.0) continue;
-        const double t = (h + 4.0) / h * (1.0 + 1.3 * cus / wgs);
+        const double t = swept / rows * (1.0 + 1.45 * cus / wgs);
         if (best_t < 0.0 || t < best_t) {
             best_t = t;
             best = h;
