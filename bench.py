@@ -235,6 +235,24 @@ def oracle_diagnostics(sc, rows):
             "sample": f"{sc.nx}x{rows} crop of the initial state, scaled x{scale:g}"}
 
 
+def cpu_one_core(sc, rows: int, nsteps: int):
+    """The oracle on one thread: `nsteps` steps of the first `rows` rows of the
+    workload (the cell-update rate does not depend on the row count)."""
+    import oracle
+    o = oracle_of(sc, rows)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.run(nsteps)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(0)
+    return {"value": sc.nx * rows * nsteps / dt, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nsteps} step(s) of a {sc.nx}x{rows} crop of the workload, 1 thread "
+                      f"({dt:.1f} s)"}
+
+
 def cpu_baseline(sc, nsteps):
     import oracle
     o = oracle_of(sc)
@@ -421,6 +439,7 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+        line["cpu_baseline_one_core"] = cpu_one_core(sc, min(sc.ny, 512), 1)
     if "fp64" in res:
         # each diagnostic reads the whole FP64 state once (6 planes x 8 B per cell)
         nbytes = 48 * N

@@ -85,6 +85,7 @@ def _load():
         lib.or_unit_hllc.argtypes = [P, D, D, D]
         lib.or_unit_sweep_line.argtypes = [P, C.c_int64, D, D, C.c_double]
         lib.or_num_threads.restype = C.c_int32
+        lib.or_set_threads.argtypes = [C.c_int32]
         lib.or_y_averages.argtypes = [P, D, D, D, D]
         lib.or_liquid_temperature.argtypes = [P, C.c_double, C.c_double, C.c_double]
         lib.or_liquid_temperature.restype = C.c_double
@@ -289,3 +290,9 @@ def log_edges(lo: float, dn: float, nbins: int) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n < 1: all
+    processors); no result depends on it."""
+    _load().or_set_threads(int(n))

@@ -786,6 +786,17 @@ int32_t or_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from now on (n < 1: all processors).  The
+ * results do not depend on it. */
+void or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n >= 1 ? (int)n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 /* ======================================================================== */
 /* Diagnostics (Sec. 4.2 transverse averages; Sec. 4.5 mass-weighted PDFs).  */
 

@@ -27,6 +27,22 @@ def test_cpu_baseline_leg_on_a_small_grid():
     assert out["kind"] == "oracle" and out["unit"] == "cell-updates/s"
     assert out["value"] > 0 and out["cores"] >= 1
     assert "96x48" in out["sample"]
+    one = bench.cpu_one_core(sc, 24, 1)
+    assert one["cores"] == 1 and one["value"] > 0 and "96x24" in one["sample"]
+    import oracle
+    assert oracle.num_threads() >= 1      # back to all processors afterwards
+
+
+def test_oracle_thread_count_changes_no_result():
+    import oracle
+    sc = S.single_bubble(nx=80, ny=40, radius=8.0, centre=(44.0, 20.0), shock_x=24.0)
+    res = []
+    for n in (1, 0):
+        oracle.set_threads(n)
+        o = bench.oracle_of(sc)
+        o.run(5)
+        res.append(o.U.copy())
+    assert np.array_equal(res[0], res[1])
 
 
 def test_cpu_baseline_leg_for_each_liquid():
