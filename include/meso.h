@@ -122,7 +122,9 @@ typedef struct {
     double cv, arr_C, arr_Ta, heat_Q;
 } mf_material;
 
-/* Uniform Cartesian grid (Sec. 3), cell sizes in metres. */
+/* Uniform Cartesian grid (Sec. 3), cell sizes in metres.  1 <= nx, ny <= 2^30
+ * and nx * ny <= 2^40; a boundary pair (lo, hi) is periodic on both sides or
+ * on neither. */
 typedef struct {
     int32_t nx, ny;
     double dx, dy;

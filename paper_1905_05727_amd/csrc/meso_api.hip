@@ -28,6 +28,7 @@ bool valid_grid(const mf_grid *g) {
         if (b[i] != MF_BC_TRANSMISSIVE && b[i] != MF_BC_PERIODIC) return false;
     if ((g->bc_xlo == MF_BC_PERIODIC) != (g->bc_xhi == MF_BC_PERIODIC)) return false;
     if ((g->bc_ylo == MF_BC_PERIODIC) != (g->bc_yhi == MF_BC_PERIODIC)) return false;
+    if (g->nx > (1 << 30) || g->ny > (1 << 30)) return false;
     if ((long long)g->nx * g->ny > (1LL << 40)) return false;
     return true;
 }
@@ -140,6 +141,9 @@ void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_optio
     d.bc_yhi = g->bc_yhi;
     d.nstrips = (g->nx + kTileW - 1) / kTileW;
     d.seg_h = seg_h > 0 ? seg_h : choose_seg_h(d.nstrips, g->ny);
+    // the segments of a strip are the launch's y dimension (at most 65535)
+    const int min_h = (g->ny + kMaxSegs - 1) / kMaxSegs;
+    if (d.seg_h < min_h) d.seg_h = min_h;
     d.nsegs = (g->ny + d.seg_h - 1) / d.seg_h;
     d.dx = g->dx;
     d.dy = g->dy;

@@ -16,6 +16,8 @@ namespace meso {
 constexpr int kThreads = 256;
 constexpr int kHalo = 2;
 constexpr int kTileW = kThreads - 2 * kHalo;
+// Largest y dimension of a launch grid: the segments of one strip.
+constexpr int kMaxSegs = 65535;
 
 // Precision modes (same numbering as MF_FP64 / MF_FP32_FP64ACC / MF_FP32).
 enum { kP64 = 0, kPMix = 1, kP32 = 2 };

@@ -57,6 +57,11 @@ def test_workspace_bytes():
     bad = reactive_pair()
     bad[1].cv = 0.0
     assert lib.mf_workspace_bytes(C.byref(g), bad, 0) == 0
+    # grid limits: each side at most 2^30, at most 2^40 cells
+    for nx, ny, ok in ((1 << 30, 1, True), ((1 << 30) + 1, 1, False), (1, (1 << 30) + 1, False),
+                       (1 << 20, 1 << 20, True), ((1 << 20) + 1, 1 << 20, False)):
+        g = meso.make_grid(nx, ny, 1.0, 1.0)
+        assert (lib.mf_workspace_bytes(C.byref(g), None, 0) > 0) == ok, (nx, ny)
 
 
 def _reactive(**kw):

@@ -116,6 +116,27 @@ def test_fp64_degenerate_grids_bitwise(shape, bc):
         assert_bitwise(s.read_conserved(), o.U, f"{nx}x{ny} {bc}")
 
 
+def test_fp64_tall_grid_within_launch_limits():
+    """A 2 x 4,500,000 column (a shock tube along y): at the height the launch
+    model prefers, one strip would need more than 65535 segments, the largest
+    y dimension of a launch; the segments grow instead and the state still
+    equals the oracle's."""
+    nx, ny = 2, 4_500_000
+    prim = S.uniform_state(nx, ny, dx=1e-3)
+    prim[0][: ny // 2] = 1 - S.Z_EPS           # air below, water above
+    prim[5][ny // 2:] = 1e9                     # 1 GPa water
+    sc = S.Scenario("tall_tube", nx, ny, 1e-3, 1e-3, prim)
+    say(f"case: tall grid {nx}x{ny}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        info = s.launch_info()
+        say("launch", info)
+        assert info["tile_h"] >= -(-ny // 65535) and info["workgroups"] <= 65535
+        s.run_steps(3)
+        o.run(3)
+        assert_bitwise(s.read_conserved(), o.U, "tall grid")
+
+
 @pytest.mark.parametrize("limiter", ["vanleer", "minmod"])
 def test_fp64_periodic_bitwise(limiter):
     sc = bubble(270, 70, periodic=True, limiter=limiter)
