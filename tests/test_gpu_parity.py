@@ -254,6 +254,50 @@ def test_fp64_roofline_8192_sampled(start):
     assert_bitwise(got, exp, "sampled 8192^2")
 
 
+def test_reduced_precision_roofline_8192():
+    """Full 8192^2 roofline workload in the benchmark's launch configuration,
+    FP32-bulk and pure FP32 against FP64 after 300 steps (relative L1: density
+    <= 1e-4, pressure <= 1e-3); then one FP32-bulk step from the FP64 state,
+    checked on sampled cells against the oracle's step with the same dt (each
+    conserved value within 1e-6 of its plane's magnitude -- 3e-8 measured: the
+    flux path is FP32, the state and its update FP64)."""
+    sc = S.roofline_8192()
+    nsteps = 300
+    say(f"case: roofline 8192x8192, {nsteps} steps, three precisions")
+    fields = {}
+    for prec in ("fp64", "fp32_fp64acc", "fp32"):
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            s.run_steps(nsteps)
+            fields[prec] = {k: s.read_field(k) for k in ("rho", "p")}
+            if prec == "fp64":
+                U0 = s.read_conserved()
+                t0, n0, _ = s.time()
+        torch.cuda.empty_cache()
+    for prec in ("fp32_fp64acc", "fp32"):
+        e_rho = rel_l1(fields[prec]["rho"], fields["fp64"]["rho"])
+        e_p = rel_l1(fields[prec]["p"], fields["fp64"]["p"])
+        say(f"{prec}: rel L1 rho {e_rho:.3e}  p {e_p:.3e}")
+        assert e_rho <= 1e-4 and e_p <= 1e-3
+    del fields
+    with meso.Solver.from_scenario(sc, precision="fp32_fp64acc") as s:
+        s.set_conserved(U0)
+        s.set_time(t0, n0)
+        s.run_steps(1)
+        U1 = s.read_conserved()
+        _, _, dt = s.time()
+    o = oracle_of(sc)
+    rng = np.random.default_rng(7)
+    n = sc.nx
+    cells = rng.integers(0, n, 4000) * n + rng.integers(0, n, 4000)
+    exp = o.step_cells(U0, n0, dt, cells)
+    got = U1.reshape(6, -1)[:, cells]
+    scale = np.abs(U0.reshape(6, -1)).max(axis=1)[:, None]
+    scale[2:4] = max(scale[2, 0], scale[3, 0], 1e-300)     # momenta on a common scale
+    err = (np.abs(got - exp) / scale).max()
+    say(f"fp32_fp64acc one step vs oracle: max scaled error {err:.3e}")
+    assert err <= 1e-6
+
+
 def first_failing_step(s, limit):
     """Steps one at a time until a sync reports a non-physical state; returns
     that step number (None if `limit` steps pass)."""
