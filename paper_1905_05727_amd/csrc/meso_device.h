@@ -337,22 +337,37 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     const R dR = SR - Rs.un;
     const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
                             L.rho * dL - Rs.rho * dR);
+    // FP64 stiffened-gas kernels: where every face of a wave takes the same
+    // star side, or none is supersonic, the wave skips the per-lane selects
+    // (same values; in the other kernels the extra code would cost occupancy)
+    constexpr bool kUniform = !FAST && EOS == 0;
     R st[NC + 1];
     if (Ss > R(0) || Ss < R(0)) {
         const bool useL = Ss > R(0);
-        Side<R, NC> K;
-        K.rho = useL ? L.rho : Rs.rho;
-        K.un = useL ? L.un : Rs.un;
-        K.ut = useL ? L.ut : Rs.ut;
-        K.p = useL ? L.p : Rs.p;
-        K.z = useL ? L.z : Rs.z;
-        K.E = useL ? L.E : Rs.E;
+        auto select_side = [&]() {
+            Side<R, NC> K;
+            K.rho = useL ? L.rho : Rs.rho;
+            K.un = useL ? L.un : Rs.un;
+            K.ut = useL ? L.ut : Rs.ut;
+            K.p = useL ? L.p : Rs.p;
+            K.z = useL ? L.z : Rs.z;
+            K.E = useL ? L.E : Rs.E;
 #pragma unroll
-        for (int c = 0; c < NC - 1; ++c) {
-            K.U[c] = useL ? L.U[c] : Rs.U[c];
-            K.F[c] = useL ? L.F[c] : Rs.F[c];
+            for (int c = 0; c < NC - 1; ++c) {
+                K.U[c] = useL ? L.U[c] : Rs.U[c];
+                K.F[c] = useL ? L.F[c] : Rs.F[c];
+            }
+            star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
+        };
+        if constexpr (kUniform) {
+            const unsigned long long act = __builtin_amdgcn_read_exec();   // lanes on this path
+            const unsigned long long onL = __builtin_amdgcn_ballot_w64(useL);
+            if (onL == act) star_flux<R, FAST, NC>(L, SL, Ss, st);
+            else if (onL == 0) star_flux<R, FAST, NC>(Rs, SR, Ss, st);
+            else select_side();
+        } else {
+            select_side();
         }
-        star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
     } else {
         // contact at rest relative to the face (every face of a region at
         // rest): average of both star branches
@@ -364,6 +379,13 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     }
     const bool supL = SL >= R(0);
     const bool supR = !supL && (SR <= R(0));
+    if constexpr (kUniform) {
+        if (__builtin_amdgcn_ballot_w64(supL || supR) == 0) {
+#pragma unroll
+            for (int c = 0; c < NC + 1; ++c) out[c] = st[c];
+            return;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[c] = supL ? L.F[c] : (supR ? Rs.F[c] : st[c]);
     out[5] = supL ? L.un : (supR ? Rs.un : st[5]);
