@@ -337,9 +337,11 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     const R dR = SR - Rs.un;
     const R Ss = Ar<R, FAST>::div((Rs.p - L.p) + (L.U[2] * dL - Rs.U[2] * dR),
                             L.rho * dL - Rs.rho * dR);
-    // FP64 stiffened-gas kernels: where every face of a wave takes the same
-    // star side, or none is supersonic, the wave skips the per-lane selects
-    // (same values; in the other kernels the extra code would cost occupancy)
+    // A wave with no supersonic face takes the star flux without the final
+    // selects; in the FP64 stiffened-gas kernels a wave whose faces all take
+    // the same star side also evaluates that side without selecting its
+    // values per lane (same values; in the other kernels that second path
+    // would cost occupancy)
     constexpr bool kUniform = !FAST && EOS == 0;
     R st[NC + 1];
     if (Ss > R(0) || Ss < R(0)) {
@@ -379,12 +381,10 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     }
     const bool supL = SL >= R(0);
     const bool supR = !supL && (SR <= R(0));
-    if constexpr (kUniform) {
-        if (__builtin_amdgcn_ballot_w64(supL || supR) == 0) {
+    if (__builtin_amdgcn_ballot_w64(supL || supR) == 0) {
 #pragma unroll
-            for (int c = 0; c < NC + 1; ++c) out[c] = st[c];
-            return;
-        }
+        for (int c = 0; c < NC + 1; ++c) out[c] = st[c];
+        return;
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[c] = supL ? L.F[c] : (supR ? Rs.F[c] : st[c]);
