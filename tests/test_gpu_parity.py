@@ -116,6 +116,27 @@ def test_fp64_degenerate_grids_bitwise(shape, bc):
         assert_bitwise(s.read_conserved(), o.U, f"{nx}x{ny} {bc}")
 
 
+@pytest.mark.parametrize("shape,rows", [((8192, 8192), 48), ((24000, 313), 20),
+                                        ((4096, 2048), 20), ((2048, 1024), 12),
+                                        ((1024, 512), 6), ((1000, 4), 1)])
+def test_segment_height_model_choices(shape, rows):
+    """The rows per workgroup segment the launch model picks on a 256-CU
+    device for the grids it was fitted on (the choices the measured kernel
+    times favour)."""
+    props = torch.cuda.get_device_properties(0)
+    if props.multi_processor_count != 256:
+        pytest.skip(f"model choices are stated for 256 compute units, not {props.multi_processor_count}")
+    nx, ny = shape
+    say(f"case: segment height {nx}x{ny}")
+    s = meso.Solver(nx, ny, 1e-3, 1e-3, precision="fp32")
+    try:
+        info = s.launch_info()
+    finally:
+        s.close()
+    assert info["tile_h"] == rows
+    assert info["workgroups"] == -(-nx // 252) * -(-ny // rows)
+
+
 def test_fp64_tall_grid_within_launch_limits():
     """A 2 x 4,500,000 column (a shock tube along y): at the height the launch
     model prefers, one strip would need more than 65535 segments, the largest
