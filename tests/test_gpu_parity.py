@@ -319,6 +319,27 @@ def test_reduced_precision_roofline_8192():
     assert err <= 1e-6
 
 
+def test_reduced_precision_paper_random_field():
+    """The paper's random cavity field (24000 x 2000, 100-cell cavities,
+    periodic top/bottom, 1 GPa water) at full size: FP32-bulk and FP32
+    against FP64 after 200 steps (relative L1: density <= 1e-4, pressure
+    <= 1e-3)."""
+    sc = S.random_cavities()
+    nsteps = 200
+    say(f"case: paper random field {sc.nx}x{sc.ny}, {nsteps} steps, three precisions")
+    fields = {}
+    for prec in ("fp64", "fp32_fp64acc", "fp32"):
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            s.run_steps(nsteps)
+            fields[prec] = {k: s.read_field(k) for k in ("rho", "p")}
+        torch.cuda.empty_cache()
+    for prec in ("fp32_fp64acc", "fp32"):
+        e_rho = rel_l1(fields[prec]["rho"], fields["fp64"]["rho"])
+        e_p = rel_l1(fields[prec]["p"], fields["fp64"]["p"])
+        say(f"{prec}: rel L1 rho {e_rho:.3e}  p {e_p:.3e}")
+        assert e_rho <= 1e-4 and e_p <= 1e-3
+
+
 def first_failing_step(s, limit):
     """Steps one at a time until a sync reports a non-physical state; returns
     that step number (None if `limit` steps pass)."""
