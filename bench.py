@@ -334,6 +334,8 @@ def main():
                     help="timed steps of each regular-array run (0: skip that section)")
     ap.add_argument("--liquids-only", action="store_true",
                     help="only the regular-array section (for profiling its kernels)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving section (for profiling the batched kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs one domain on one GPU; multi-GPU runs are not "
@@ -349,6 +351,10 @@ def main():
     modes = [m for m in args.modes.split(",") if m]
     if args.liquids_only:
         print(json.dumps({"liquids": liquids_bench(modes, args.liquid_steps, args.warmup, 0)}),
+              flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serving_requests, args.serving_steps)}),
               flush=True)
         return
 
