@@ -237,11 +237,16 @@ int32_t mf_enable_timing(mf_solver *s, int32_t enable);
 int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches);
 
 /* Kernel launch geometry of the state-update kernel for this solver:
- * workgroups, threads per workgroup, and the number of cells one workgroup
- * writes (strip width x segment height).  The segment height is chosen at
- * creation from the grid and the device's compute units (short segments for
- * small grids, so that every compute unit gets several workgroups); the
- * environment variable MESO_SEG_H (>= 1) fixes it.  No result depends on it. */
+ * workgroups, threads per workgroup, and the number of cells one leading
+ * workgroup writes (strip width x segment height).  The segment height is
+ * chosen at creation from the grid, the precision mode and the device's
+ * compute units (short segments for small grids, so that every compute unit
+ * gets several workgroups; on large grids taller segments down to a tail of
+ * shorter ones, dispatched last, which evens out the end of the launch).  The
+ * environment variable MESO_SEG_H (>= 1) fixes a uniform height, and
+ * MESO_SEG_TAPER = "h2,rows" gives the last `rows` or more rows segments of h2
+ * rows (h2 below the leading height; "0,0": none).  No result depends on
+ * either. */
 int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int32_t *tile_w,
                        int32_t *tile_h);
 

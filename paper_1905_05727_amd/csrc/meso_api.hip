@@ -8,6 +8,7 @@
 #include "meso_internal.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -116,13 +117,40 @@ int seg_h_model(const int *nstrips, const int *ny, int n, int cus) {
     return best;
 }
 
-int choose_seg_h(int nstrips, int ny) {
-    const char *env = getenv("MESO_SEG_H");
-    if (env) {
-        const int v = atoi(env);
-        if (v >= 1) return v;
-    }
-    return seg_h_model(&nstrips, &ny, 1, device_cus());
+void seg_taper(int nstrips, int ny, int cus, int prec, int &h, int &h2, int &tail_rows) {
+    // Grids that the uniform model gives tall segments (>= 20 rows) do better
+    // with taller segments still and a tail of short ones dispatched last:
+    // rows h (32 or 64) down to a tail of h/5-row segments, about 3 workgroups
+    // per compute unit in all (8 to 32 per strip, at most a fifth of the
+    // rows).  Measured on MI355X against the uniform choice: 1.5-5 % faster
+    // on 8192 x 8192, 4096 x 2048, 24000 x 313 and 24000 x 2000 in every mode
+    // but one: the FP32-bulk kernel on grids under 32 strips (4 % slower on
+    // 4096 x 2048), which keeps uniform segments.
+    h2 = tail_rows = 0;
+    if (h < 20) return;
+    if (prec == MF_FP32_FP64ACC && nstrips < 32) return;
+    if (cus <= 0) cus = 256;
+    const int H = h >= 40 ? 64 : 32;
+    const int t2 = H / 5;
+    int n2 = (3 * cus + nstrips - 1) / nstrips;
+    n2 = n2 < 8 ? 8 : (n2 > 32 ? 32 : n2);
+    if ((long long)n2 * t2 * 5 > ny) return;
+    h = H;
+    h2 = t2;
+    tail_rows = n2 * t2;
+}
+
+void set_segments(Desc &d, int ny, int h, int h2, int tail_rows) {
+    d.seg_h = d.seg_h2 = h;
+    d.nsegs = d.seg_n1 = (ny + h - 1) / h;
+    if (h2 < 1 || h2 >= h || tail_rows <= 0) return;
+    const int n1 = (ny - tail_rows) / h;   // whole tall segments ahead of the tail
+    if (n1 < 1) return;
+    const long long n = (long long)n1 + (ny - (long long)n1 * h + h2 - 1) / h2;
+    if (n > kMaxSegs) return;
+    d.seg_n1 = n1;
+    d.seg_h2 = h2;
+    d.nsegs = (int)n;
 }
 
 void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,
@@ -140,11 +168,24 @@ void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_optio
     d.bc_ylo = g->bc_ylo;
     d.bc_yhi = g->bc_yhi;
     d.nstrips = (g->nx + kTileW - 1) / kTileW;
-    d.seg_h = seg_h > 0 ? seg_h : choose_seg_h(d.nstrips, g->ny);
+    int h = seg_h, h2 = 0, tail = 0;
+    if (h <= 0) {
+        const char *fix = getenv("MESO_SEG_H");
+        if (fix && atoi(fix) >= 1) {
+            h = atoi(fix);
+        } else {
+            const int cus = device_cus();
+            h = seg_h_model(&d.nstrips, &g->ny, 1, cus);
+            seg_taper(d.nstrips, g->ny, cus, opt->precision, h, h2, tail);
+        }
+    }
+    if (const char *env = getenv("MESO_SEG_TAPER")) {
+        if (sscanf(env, "%d,%d", &h2, &tail) != 2) h2 = tail = 0;
+    }
     // the segments of a strip are the launch's y dimension (at most 65535)
     const int min_h = (g->ny + kMaxSegs - 1) / kMaxSegs;
-    if (d.seg_h < min_h) d.seg_h = min_h;
-    d.nsegs = (g->ny + d.seg_h - 1) / d.seg_h;
+    if (h < min_h) h = min_h;
+    set_segments(d, g->ny, h, h2, tail);
     d.dx = g->dx;
     d.dy = g->dy;
     d.cfl = opt->cfl;

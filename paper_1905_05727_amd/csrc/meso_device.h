@@ -668,8 +668,9 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     // SKIP: a wave whose first column lies beyond the grid's last halo column
     // does no arithmetic (the mostly empty last strip of a small grid)
     [[maybe_unused]] const bool idle = SKIP && (x0 - kHalo + (t & ~63) >= d.nx + kHalo);
-    const int y0 = by * d.seg_h;
-    const int y1 = min(y0 + d.seg_h, d.ny);
+    const bool head = by < d.seg_n1;
+    const int y0 = head ? by * d.seg_h : d.seg_n1 * d.seg_h + (by - d.seg_n1) * d.seg_h2;
+    const int y1 = min(y0 + (head ? d.seg_h : d.seg_h2), d.ny);
     const S zlo = (S)d.zlo, zhi = (S)d.zhi, idx = (S)d.idx, idy = (S)d.idy;
 
     S smax = S(0);

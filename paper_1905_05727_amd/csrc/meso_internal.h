@@ -49,6 +49,10 @@ struct Desc {
     long long plane;         // elements per plane
     int bc_xlo, bc_xhi, bc_ylo, bc_yhi;
     int nstrips, nsegs;
+    // segments 0 .. seg_n1-1 are seg_h rows tall, the rest (from row
+    // seg_n1 * seg_h on, dispatched last) seg_h2 rows: a tail of short
+    // segments evens out the end of a launch
+    int seg_n1, seg_h2;
     double dx, dy, cfl;      // cell sizes and CFL number (used by the batched dt kernel)
     double idx, idy;         // 1/dx, 1/dy
     double zlo, zhi;         // eps, 1 - eps of the pointwise stage
@@ -74,11 +78,17 @@ int planes_of(const mf_material *mat);
 bool valid_scheme(const mf_options *opt);
 // bytes of one pitched state copy (nc planes), 256-byte rounded
 size_t state_bytes(const mf_grid *g, int prec, int nc);
-// Rows per workgroup segment: for one grid (MESO_SEG_H >= 1 in the
-// environment fixes it), and for one launch over n grids of nstrips[i] strips
-// and ny[i] rows on a device of `cus` compute units (0: 256).
-int choose_seg_h(int nstrips, int ny);
+// Uniform rows per workgroup segment for one launch over n grids of
+// nstrips[i] strips and ny[i] rows on a device of `cus` compute units (0: 256).
 int seg_h_model(const int *nstrips, const int *ny, int n, int cus);
+// The tail for one grid whose uniform model height is h, in precision mode
+// prec (MF_FP*); updates h, and sets h2 = 0 when the grid keeps uniform
+// segments.
+void seg_taper(int nstrips, int ny, int cus, int prec, int &h, int &h2, int &tail_rows);
+// Segments of one grid: h rows each, or (1 <= h2 < h, tail_rows > 0) h rows
+// down to the last tail_rows or more rows, which get h2-row segments;
+// uniform if the tail would not fit or exceed the launch's segment limit.
+void set_segments(Desc &d, int ny, int h, int h2, int tail_rows);
 int device_cus();
 // Fill a descriptor for a solve whose workspace (control block + two state
 // copies) starts at base.

@@ -333,8 +333,7 @@ int32_t rebuild_tables(mf_server *s) {
         const int h = class_seg_h(s, members);
         for (Slot *psl : members) {
             Slot &sl = *psl;
-            sl.d.seg_h = h;
-            sl.d.nsegs = (sl.d.ny + h - 1) / h;
+            meso::set_segments(sl.d, sl.d.ny, h, 0, 0);
             const int k = (int)descs.size();
             descs.push_back(sl.d);
             for (int by = 0; by < sl.d.nsegs; ++by)

@@ -116,25 +116,62 @@ def test_fp64_degenerate_grids_bitwise(shape, bc):
         assert_bitwise(s.read_conserved(), o.U, f"{nx}x{ny} {bc}")
 
 
-@pytest.mark.parametrize("shape,rows", [((8192, 8192), 48), ((24000, 313), 20),
-                                        ((4096, 2048), 20), ((2048, 1024), 12),
-                                        ((1024, 512), 6), ((1000, 4), 1)])
-def test_segment_height_model_choices(shape, rows):
-    """The rows per workgroup segment the launch model picks on a 256-CU
-    device for the grids it was fitted on (the choices the measured kernel
-    times favour)."""
+# (grid, precision, rows of the leading segments, workgroups): grids the
+# uniform model gives >= 20-row segments get taller ones and a tail of short
+# segments (h/5 rows) dispatched last, except the FP32-bulk kernel on grids
+# under 32 strips
+SEG_CASES = [((8192, 8192), "fp32", 64, 33 * (123 + 27)),
+             ((8192, 8192), "fp64", 64, 33 * (123 + 27)),
+             ((24000, 313), "fp32", 32, 96 * (8 + 10)),
+             ((24000, 2000), "fp32_fp64acc", 64, 96 * (30 + 11)),
+             ((4096, 2048), "fp32", 32, 17 * (58 + 32)),
+             ((4096, 2048), "fp32_fp64acc", 20, 17 * 103),
+             ((2048, 1024), "fp32", 12, 9 * 86),
+             ((1024, 512), "fp32", 6, 5 * 86),
+             ((1000, 4), "fp32", 1, 4 * 4)]
+
+
+@pytest.mark.parametrize("shape,prec,rows,workgroups", SEG_CASES)
+def test_segment_height_model_choices(shape, prec, rows, workgroups):
+    """The segments the launch model picks on a 256-CU device for the grids it
+    was fitted on (the choices the measured kernel times favour)."""
     props = torch.cuda.get_device_properties(0)
     if props.multi_processor_count != 256:
         pytest.skip(f"model choices are stated for 256 compute units, not {props.multi_processor_count}")
     nx, ny = shape
-    say(f"case: segment height {nx}x{ny}")
-    s = meso.Solver(nx, ny, 1e-3, 1e-3, precision="fp32")
+    say(f"case: segment height {nx}x{ny} {prec}")
+    s = meso.Solver(nx, ny, 1e-3, 1e-3, precision=prec)
     try:
         info = s.launch_info()
     finally:
         s.close()
-    assert info["tile_h"] == rows
-    assert info["workgroups"] == -(-nx // 252) * -(-ny // rows)
+    assert (info["tile_h"], info["workgroups"]) == (rows, workgroups)
+
+
+@pytest.mark.parametrize("h,taper", [("16", "4,64"), ("24", "1,10"), ("8", "3,500"),
+                                     ("64", "63,64"), ("32", "6,1000")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_segment_tail_changes_no_value(h, taper, prec, monkeypatch):
+    """Leading segments of h rows and a tail of shorter ones (MESO_SEG_TAPER
+    = tail height, tail rows) give the state of uniform segments bit for bit
+    (the last case's tail does not fit and leaves the segments uniform)."""
+    sc = S.single_bubble()
+    say(f"case: segment tail h={h} tail={taper} {prec}")
+    monkeypatch.setenv("MESO_SEG_H", "6")
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(40)
+        ref = s.read_conserved()
+    monkeypatch.setenv("MESO_SEG_H", h)
+    monkeypatch.setenv("MESO_SEG_TAPER", taper)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        info = s.launch_info()
+        s.run_steps(40)
+        got = s.read_conserved()
+    h2, tail = (int(v) for v in taper.split(","))
+    n1 = (sc.ny - tail) // int(h)
+    nseg = n1 + -(-(sc.ny - n1 * int(h)) // h2) if n1 >= 1 else -(-sc.ny // int(h))
+    assert info["workgroups"] == -(-sc.nx // 252) * nseg
+    assert np.array_equal(got, ref)
 
 
 def test_fp64_tall_grid_within_launch_limits():
