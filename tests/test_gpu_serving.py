@@ -168,26 +168,34 @@ def test_serving_workload_sizes_alone_equals_in_mix():
         assert nb == n == nsteps and tb == t and np.array_equal(U, Ub)
 
 
+SEG_SERVE = [(None, None), ("1", None), ("4", None), ("64", None), ("16", "4,16"),
+             ("64", "2,8"), ("12", "0,0")]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_segment_height_changes_no_value(prec, monkeypatch):
     """The server picks the rows per workgroup segment from the load; fixing
-    it at 1, 4 or 64 rows (MESO_SERVE_SEG_H) gives the same bits as the
-    automatic choice."""
+    it at 1, 4 or 64 rows (MESO_SERVE_SEG_H), or giving each solve a tail of
+    shorter segments dispatched last (MESO_SERVE_TAPER), gives the same bits
+    as the automatic choice."""
     reqs = small_requests(6, seed=11)
     nsteps = 23
     res = {}
-    for seg in (None, "1", "4", "64"):
-        if seg is None:
-            monkeypatch.delenv("MESO_SERVE_SEG_H", raising=False)
-        else:
-            monkeypatch.setenv("MESO_SERVE_SEG_H", seg)
-        say(f"case: 6 requests {[r.nx for r in reqs]}, {nsteps} steps, {prec}, segment {seg}")
+    for seg, taper in SEG_SERVE:
+        for var, val in (("MESO_SERVE_SEG_H", seg), ("MESO_SERVE_TAPER", taper)):
+            if val is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, val)
+        say(f"case: 6 requests {[r.nx for r in reqs]}, {nsteps} steps, {prec}, segment {seg}, "
+            f"tail {taper}")
         with serve.Server(1 << 30, max_slots=4, precision=prec, max_inflight=3) as srv:
             tickets = [srv.submit(sc, nsteps) for sc in reqs]
             srv.drain()
-            res[seg] = [srv.result(tk) for tk in tickets]
+            res[(seg, taper)] = [srv.result(tk) for tk in tickets]
     monkeypatch.delenv("MESO_SERVE_SEG_H", raising=False)
-    for seg in ("1", "4", "64"):
-        for (a, ta, na), (b, tb, nb) in zip(res[None], res[seg]):
+    monkeypatch.delenv("MESO_SERVE_TAPER", raising=False)
+    for key in SEG_SERVE[1:]:
+        for (a, ta, na), (b, tb, nb) in zip(res[(None, None)], res[key]):
             assert na == nb == nsteps and ta == tb
             assert np.array_equal(a, b)
