@@ -141,6 +141,7 @@ void seg_taper(int nstrips, int ny, int cus, int prec, int &h, int &h2, int &tai
 }
 
 void set_segments(Desc &d, int ny, int h, int h2, int tail_rows) {
+    if (h > ny) h = ny;   // one segment covers the strip (and ny + h - 1 stays in range)
     d.seg_h = d.seg_h2 = h;
     d.nsegs = d.seg_n1 = (ny + h - 1) / h;
     if (h2 < 1 || h2 >= h || tail_rows <= 0) return;

@@ -174,6 +174,23 @@ def test_segment_tail_changes_no_value(h, taper, prec, monkeypatch):
     assert np.array_equal(got, ref)
 
 
+def test_fixed_segment_height_beyond_grid(monkeypatch):
+    """A fixed height larger than the grid (MESO_SEG_H near the int32 limit)
+    gives one segment per strip and the same state as the automatic choice."""
+    sc = bubble(300, 200)
+    say("case: MESO_SEG_H=2000000000 on 300x200")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(10)
+        ref = s.read_conserved()
+    monkeypatch.setenv("MESO_SEG_H", "2000000000")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        info = s.launch_info()
+        s.run_steps(10)
+        got = s.read_conserved()
+    assert info["tile_h"] == 200 and info["workgroups"] == 2
+    assert np.array_equal(got, ref)
+
+
 def test_fp64_tall_grid_within_launch_limits():
     """A 2 x 4,500,000 column (a shock tube along y): at the height the launch
     model prefers, one strip would need more than 65535 segments, the largest
