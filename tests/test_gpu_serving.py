@@ -56,6 +56,28 @@ def test_alone_equals_in_mix(prec):
         assert np.array_equal(o.U, got[0][0])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
+def test_loaded_server_tail_equals_alone(prec, monkeypatch):
+    """Sixteen 512^2 solves admitted together: the load gives 16-row segments
+    (the segment model over 16 grids of 3 strips), so each solve's last 16
+    rows go into 4-row segments dispatched after all the others.  Every
+    result equals its lone solve bit for bit."""
+    monkeypatch.delenv("MESO_SERVE_SEG_H", raising=False)
+    monkeypatch.delenv("MESO_SERVE_TAPER", raising=False)
+    reqs = small_requests(16, seed=5, sizes=(512,))
+    nsteps = 12
+    say(f"case: 16 requests of 512^2, {nsteps} steps, {prec}")
+    with serve.Server(2 << 30, max_slots=16, precision=prec, max_inflight=3) as srv:
+        tickets = [srv.submit(sc, nsteps) for sc in reqs]
+        srv.drain()
+        got = [srv.result(tk) for tk in tickets]
+    for k, sc in enumerate(reqs):
+        U, t, n = serve.solve_alone(sc, nsteps, precision=prec)
+        Ub, tb, nb = got[k]
+        assert n == nb == nsteps and t == tb
+        assert np.array_equal(U, Ub), f"request {k} differs under load"
+
+
 def test_mixed_liquids_alone_equals_in_mix():
     """Water and nitromethane requests in one server: each tick runs one
     batched launch per liquid; every result equals its lone solve."""
