@@ -339,8 +339,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs one domain on one GPU; multi-GPU runs are not "
-              "part of this build (see the sharding design notes). Use --gpus 1.",
-              file=sys.stderr)
+              "supported (the domain decomposition over several GPUs is a design, not code). "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
