@@ -242,54 +242,84 @@ __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
 // fixed order (increasing j inside a column, then increasing i), so the
 // results do not depend on the launch geometry.
 
-// One thread per column: out[0..2][i] = pbar, rhobar, density-weighted ubar;
-// out[3+c][i] = sum over the column of conserved component c.  One wave per
-// workgroup spreads the columns over as many compute units as possible; the
-// loads of kColRows rows are issued before their sums, which still run one
-// row after the other in increasing j.
-constexpr int kColRows = 16;
+// Column pass: out[0..2][i] = pbar, rhobar, density-weighted ubar; out[3+c][i]
+// = sum over the column of conserved component c.  A workgroup takes kColW
+// columns in blocks of kColRows rows.  Its four waves load a block (all of a
+// thread's rows issued before any is converted) and write each cell's
+// components, pressure and z1rho1 + z2rho2 to LDS; then each group of kColW
+// threads adds one of the column sums over the block's rows in increasing j.
+// Every sum therefore runs in the order of one sequential pass down the
+// column, while the per-cell work is spread over all the waves.
+constexpr int kColRows = 24;
+constexpr int kColW = 32;
+constexpr int kColThreads = 256;
+constexpr int kColGroups = kColThreads / kColW;          // 8
+constexpr int kColPerThread = kColRows / kColGroups;     // 3 rows per thread and block
 
 template <class S, int NC>
-__global__ __launch_bounds__(64) void column_kernel(Desc d, int src_idx, double *out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.nx) return;
+__global__ __launch_bounds__(kColThreads) void column_kernel(Desc d, int src_idx, double *out) {
+    // [row][quantity][column]; quantities 0..NC-1 the components, NC the
+    // pressure, NC+1 the density
+    __shared__ double sv[kColRows][NC + 2][kColW];
+    __shared__ double fin[NC + 2][kColW];
+    const int t = threadIdx.x;
+    const int cl = t % kColW;
+    const int g = t / kColW;
+    const int i = blockIdx.x * kColW + cl;
+    const bool in = i < d.nx;
     const S *src = (const S *)d.buf[src_idx];
     const Mix<double> m = mix_of<double>(d);
-    double sp = 0.0, sr = 0.0, sm = 0.0, sc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int j, double q[7]) {
-        const long long o = (long long)j * d.pitch + i;
+    // group g sums quantity qa (the pressure, the density, then the
+    // components); with NC = 7 group 0 also sums component 6
+    const int qa = g == 0 ? NC : (g == 1 ? NC + 1 : g - 2);
+    double sa = 0.0, sb = 0.0;
+    for (int j0 = 0; j0 < d.ny; j0 += kColRows) {
+        const int nr = min(kColRows, d.ny - j0);
+        double q[kColPerThread][7];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = (double)src[c * d.plane + o];
-        if constexpr (NC == 6) q[6] = 0.0;
-    };
-    auto add = [&](const double q[7]) {
-        double w[6], r, rc2;
-        cons_to_prim<double, false, 6>(m, q, w, r, rc2);
-        sp = sp + w[4];
-        sr = sr + (q[0] + q[1]);
-        sm = sm + q[2];
+        for (int u = 0; u < kColPerThread; ++u) {
+            const int r = g + u * kColGroups;
+            if (in && r < nr) {
+                const long long o = (long long)(j0 + r) * d.pitch + i;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sc[c] = sc[c] + q[c];
-    };
-    int j = 0;
-    for (; j + kColRows <= d.ny; j += kColRows) {
-        double q[kColRows][7];
+                for (int c = 0; c < NC; ++c) q[u][c] = (double)src[c * d.plane + o];
+            }
+            if constexpr (NC == 6) q[u][6] = 0.0;
+        }
 #pragma unroll
-        for (int u = 0; u < kColRows; ++u) load(j + u, q[u]);
+        for (int u = 0; u < kColPerThread; ++u) {
+            const int r = g + u * kColGroups;
+            if (in && r < nr) {
+                double w[6], rr, rc2;
+                cons_to_prim<double, false, 6>(m, q[u], w, rr, rc2);
 #pragma unroll
-        for (int u = 0; u < kColRows; ++u) add(q[u]);
+                for (int c = 0; c < NC; ++c) sv[r][c][cl] = q[u][c];
+                sv[r][NC][cl] = w[4];
+                sv[r][NC + 1][cl] = q[u][0] + q[u][1];
+            }
+        }
+        __syncthreads();
+        if (in) {
+            for (int r = 0; r < nr; ++r) {
+                sa = sa + sv[r][qa][cl];
+                if constexpr (NC == 7) {
+                    if (g == 0) sb = sb + sv[r][6][cl];
+                }
+            }
+        }
+        __syncthreads();
     }
-    for (; j < d.ny; ++j) {
-        double q[7];
-        load(j, q);
-        add(q);
+    fin[qa][cl] = sa;
+    if constexpr (NC == 7) {
+        if (g == 0) fin[6][cl] = sb;
     }
+    __syncthreads();
+    if (!in) return;
     const long long n = d.nx;
-    out[i] = sp / (double)d.ny;
-    out[n + i] = sr / (double)d.ny;
-    out[2 * n + i] = sm / sr;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) out[(3 + c) * n + i] = sc[c];
+    if (g == 0) out[i] = fin[NC][cl] / (double)d.ny;
+    if (g == 1) out[n + i] = fin[NC + 1][cl] / (double)d.ny;
+    if (g == 2) out[2 * n + i] = fin[2][cl] / fin[NC + 1][cl];
+    for (int c = g; c < NC; c += kColGroups) out[(3 + c) * n + i] = fin[c][cl];
 }
 
 // Domain integrals from the column sums: thread c sums component c's column
@@ -463,11 +493,11 @@ hipError_t launch_read_field(const Desc &d, int prec, int src, int field, double
 
 
 hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStream_t st) {
-    const int g = (d.nx + 63) / 64;
+    const int g = (d.nx + kColW - 1) / kColW;
     void (*k)(Desc, int, double *);
     if (prec == kP32) k = d.nc == 7 ? column_kernel<float, 7> : column_kernel<float, 6>;
     else k = d.nc == 7 ? column_kernel<double, 7> : column_kernel<double, 6>;
-    hipLaunchKernelGGL(k, dim3(g), dim3(64), 0, st, d, src, out);
+    hipLaunchKernelGGL(k, dim3(g), dim3(kColThreads), 0, st, d, src, out);
     return hipGetLastError();
 }
 

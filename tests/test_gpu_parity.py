@@ -626,13 +626,15 @@ def test_nonfinite_state_is_reported():
 
 
 # ------------------------------------------------------------ diagnostics ----
+@pytest.mark.parametrize("shape", [(300, 140), (40, 9), (33, 49)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
-def test_diagnostics_match_oracle(prec):
+def test_diagnostics_match_oracle(prec, shape):
     """Transverse averages, integrals (fixed summation order: bitwise) and the
     mass-weighted log-binned pressure PDF (bin decisions exact, bin masses to
-    1e-12) of the stored state, against the oracle on the same values."""
-    sc = bubble(300, 140)
-    say(f"case: diagnostics 300x140 {prec}")
+    1e-12) of the stored state, against the oracle on the same values (grids
+    with a ragged last block of columns and of rows)."""
+    sc = bubble(*shape)
+    say(f"case: diagnostics {shape[0]}x{shape[1]} {prec}")
     with meso.Solver.from_scenario(sc, precision=prec) as s:
         s.run_steps(60)
         U = s.read_conserved()
