@@ -249,7 +249,8 @@ __global__ void read_field_kernel(Desc d, int src_idx, int field, double *out) {
 // components, pressure and z1rho1 + z2rho2 to LDS; then each group of kColW
 // threads adds one of the column sums over the block's rows in increasing j.
 // Every sum therefore runs in the order of one sequential pass down the
-// column, while the per-cell work is spread over all the waves.
+// column, while the per-cell work is spread over all the waves; the loads of
+// the next block are issued before a block is converted.
 constexpr int kColRows = 24;
 constexpr int kColW = 32;
 constexpr int kColThreads = 256;
@@ -273,19 +274,24 @@ __global__ __launch_bounds__(kColThreads) void column_kernel(Desc d, int src_idx
     // components); with NC = 7 group 0 also sums component 6
     const int qa = g == 0 ? NC : (g == 1 ? NC + 1 : g - 2);
     double sa = 0.0, sb = 0.0;
-    for (int j0 = 0; j0 < d.ny; j0 += kColRows) {
-        const int nr = min(kColRows, d.ny - j0);
-        double q[kColPerThread][7];
+    // a thread's rows of the block at j0, loaded into q; rows and columns
+    // beyond the grid load its last row or column (always in bounds, never
+    // used), so every load is issued unconditionally and the next block's
+    // loads stay in flight while a block is converted
+    const int ic = in ? i : d.nx - 1;
+    auto issue = [&](int j0, double (&q)[kColPerThread][7]) {
 #pragma unroll
         for (int u = 0; u < kColPerThread; ++u) {
-            const int r = g + u * kColGroups;
-            if (in && r < nr) {
-                const long long o = (long long)(j0 + r) * d.pitch + i;
+            const int row = min(j0 + g + u * kColGroups, d.ny - 1);
+            const long long o = (long long)row * d.pitch + ic;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) q[u][c] = (double)src[c * d.plane + o];
-            }
+            for (int c = 0; c < NC; ++c) q[u][c] = (double)src[c * d.plane + o];
             if constexpr (NC == 6) q[u][6] = 0.0;
         }
+    };
+    // convert the block at j0 into LDS and add it to the sums
+    auto consume = [&](int j0, double (&q)[kColPerThread][7]) {
+        const int nr = min(kColRows, d.ny - j0);
 #pragma unroll
         for (int u = 0; u < kColPerThread; ++u) {
             const int r = g + u * kColGroups;
@@ -308,6 +314,18 @@ __global__ __launch_bounds__(kColThreads) void column_kernel(Desc d, int src_idx
             }
         }
         __syncthreads();
+    };
+    // two register sets: block j1's loads are issued before block j0 is
+    // converted and summed
+    double bufA[kColPerThread][7], bufB[kColPerThread][7];
+    issue(0, bufA);
+    for (int j0 = 0; j0 < d.ny; j0 += 2 * kColRows) {
+        const int j1 = j0 + kColRows;
+        if (j1 < d.ny) issue(j1, bufB);
+        consume(j0, bufA);
+        if (j1 >= d.ny) break;
+        if (j1 + kColRows < d.ny) issue(j1 + kColRows, bufA);
+        consume(j1, bufB);
     }
     fin[qa][cl] = sa;
     if constexpr (NC == 7) {
