@@ -378,9 +378,14 @@ __global__ __launch_bounds__(kThreads) void histo_kernel(Desc d, int src_idx, in
     const Mix<double> m = mix_of<double>(d);
     const Rx<double> rx = rx_of<double>(d);
     const long long N = (long long)d.nx * d.ny;
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
-         k += (long long)gridDim.x * blockDim.x) {
-        const int j = (int)(k / d.nx), i = (int)(k - (long long)j * d.nx);
+    // grid-stride loop over the cells; (j, i) advance with the stride (one
+    // carry, since the stride's column part is below nx) instead of a 64-bit
+    // division per cell
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long k0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int sj = (int)(stride / d.nx), si = (int)(stride - (long long)sj * d.nx);
+    int j = (int)(k0 / d.nx), i = (int)(k0 - (long long)j * d.nx);
+    for (long long k = k0; k < N; k += stride) {
         const long long o = (long long)j * d.pitch + i;
         double q[7], v;
         if (field == MF_QDOT) {
@@ -394,14 +399,21 @@ __global__ __launch_bounds__(kThreads) void histo_kernel(Desc d, int src_idx, in
             cons_to_prim<double, false, 6>(m, q, w, r, rc2);
             v = (field == 6) ? (q[0] + q[1]) : w[4];
         }
-        if (!(v >= e[0]) || !(v < e[nbins])) continue;
-        int a = 0, z = nbins;
-        while (z - a > 1) {
-            const int hh = (a + z) / 2;
-            if (e[hh] <= v) a = hh;
-            else z = hh;
+        if (v >= e[0] && v < e[nbins]) {
+            int a = 0, z = nbins;
+            while (z - a > 1) {
+                const int hh = (a + z) / 2;
+                if (e[hh] <= v) a = hh;
+                else z = hh;
+            }
+            atomicAdd(&h[a], q[1] * area);
         }
-        atomicAdd(&h[a], q[1] * area);
+        i += si;
+        j += sj;
+        if (i >= d.nx) {
+            i -= d.nx;
+            ++j;
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbins; b += blockDim.x)
