@@ -24,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+SOURCE = _SRC
 _LIB = os.path.join(_HERE, "_oracle.so")
 
 TRANSMISSIVE = 0
@@ -32,15 +33,26 @@ VANLEER = 0
 MINMOD = 1
 
 
+GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-std=c99"]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into _oracle.so (gcc, FP64, no contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-               "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", *GCC_FLAGS, "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_variant(src: str, out: str, extra=()) -> str:
+    """Compile another copy of the oracle's source (a test's planted mistake,
+    or extra flags such as sanitizers) into the shared library `out`; load it
+    in a separate process by setting MESO_ORACLE_LIB=out."""
+    cmd = ["gcc", *GCC_FLAGS, *extra, "-shared", "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
 
 
 class _Problem(C.Structure):
@@ -61,9 +73,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = C.CDLL(_LIB)
+        path = os.environ.get("MESO_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = C.CDLL(path)
         P = C.POINTER(_Problem)
         D = C.POINTER(C.c_double)
         I64 = C.POINTER(C.c_int64)
