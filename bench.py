@@ -3,16 +3,20 @@
 
 Workload (default): the 8192 x 8192 roofline case -- 2000 seeded air bubbles
 (radius U[16, 48] cells) in water hit by a planar 1 GPa shock, transmissive
-walls, CFL 0.4 -- advanced in FP64, FP32-bulk/FP64-accumulate and pure FP32.
-A step is one pass of the whole hot path: CFL time step from the device-side
-maximum, both split sweeps (MUSCL-Hancock + HLLC + non-conservative z1 term),
-the pointwise stage and the next step's CFL maximum.  Inputs are resident in
-HBM before the timed region starts.
+walls, CFL 0.4 -- advanced in fast FP64 (FP64 with Newton-refined hardware
+divisions and square roots, within 1e-12 of the FP64 contract), FP64 (the
+contract bit for bit), FP32-bulk/FP64-accumulate and pure FP32.  A step is one
+pass of the whole hot path: CFL time step from the device-side maximum, both
+split sweeps (MUSCL-Hancock + HLLC + non-conservative z1 term), the pointwise
+stage and the next step's CFL maximum.  Inputs are resident in HBM before the
+timed region starts.
 
-Prints ONE JSON line.  The FP64 mode is the headline `value`; the other modes
-are reported under "modes", the serving benchmark under "serving", and the
-paper's regular cavity array in water, inert and reacting nitromethane under
-"liquids".
+Prints ONE JSON line.  The fast FP64 mode is the headline `value` and its
+state-update kernel the `roofline` (HBM bound: one read and one write of the
+state per step against 8 TB/s, the library's copy kernel beside it as the
+achievable ceiling); the other modes are reported under "modes", the serving
+benchmark under "serving", and the paper's regular cavity array in water,
+inert and reacting nitromethane under "liquids".
 """
 from __future__ import annotations
 
@@ -30,16 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-# VALU issue peak for un-fused operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
-# (the published 78.6 TFLOP/s FP64 / 157.3 TFLOP/s FP32 count a fused
-# multiply-add, resp. a packed pair, as two or four flops)
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# floating-point operations of one cell-step, counted from the arithmetic
-# contract (division and square root count as one): 2 sweeps x (closure 23 +
-# reconstruction/predictor 92 + HLLC 116 + update 22) + epilogue 35
-OPS_PER_CELL = 541
-BYTES_PER_CELL = {"fp64": 96, "fp32_fp64acc": 96, "fp32": 48}   # 1 read + 1 write of 6 planes
-DTYPE = {"fp64": "f64", "fp32_fp64acc": "f32/f64", "fp32": "f32"}
+# One wave64 VALU instruction per SIMD every 4 cycles: 256 CU x 4 SIMD x 16
+# lanes x 2.4 GHz lane-instructions/s (a diagnostic of how busy the issue
+# slots are; the published 78.6 TFLOP/s FP64 counts a fused multiply-add as two)
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12
+BYTES_PER_CELL = {"fp64": 96, "fp64_fast": 96, "fp32_fp64acc": 96, "fp32": 48}   # 1 read + 1 write of 6 planes
+DTYPE = {"fp64": "f64", "fp64_fast": "f64", "fp32_fp64acc": "f32/f64", "fp32": "f32"}
 METRIC = "cell-updates/s/GPU FP32 vs FP64 (+% HBM roofline); batched p50/p99 latency"
 
 
@@ -52,6 +52,7 @@ def kernel_source_hash() -> str:
     comment edit does not invalidate a counter summary of the same code)."""
     h = hashlib.sha256()
     for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip",
+              "meso_kernels_fast64.hip",
               "meso_kernels_react.hip", "meso_kernels_react_fast.hip", "meso_internal.h",
               "meso_api.hip"):
         text = open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f)).read()
@@ -104,7 +105,7 @@ def time_diagnostics(obj, reps: int):
     return out
 
 
-def run_mode(sc, prec, steps, warmup, ref=None, diagnostics=False):
+def run_mode(sc, prec, steps, warmup, diagnostics=False, active=None):
     import torch
     from paper_1905_05727_amd import meso
     s = meso.Solver.from_scenario(sc, precision=prec)
@@ -125,32 +126,63 @@ def run_mode(sc, prec, steps, warmup, ref=None, diagnostics=False):
     out["fields"] = {k: s.read_field(k) for k in ("rho", "p")}
     if diagnostics:
         out["diagnostics_ms"] = time_diagnostics(s, 5)
+    if active and active[0] > nstep:
+        # a later window of the same run, where the shock has crossed more of
+        # the field and more faces carry flow (the timed window above is the
+        # near-rest start of the run)
+        s.run_steps(active[0] - nstep)
+        s.sync()
+        s.enable_timing(True)
+        s.run_steps(active[1])
+        s.sync()
+        kms2, l2 = s.kernel_time()
+        out["active"] = {"from_step": active[0], "steps": active[1],
+                         "kernel_ms_avg": kms2 / max(l2, 1)}
     s.close()
     torch.cuda.empty_cache()
     return out
 
 
 def copy_bandwidth(gib: float = 2.0, reps: int = 5):
-    """Plain device-to-device copy of a known size: the achievable HBM ceiling
-    and the reference against which rocprofv3's FETCH_SIZE / WRITE_SIZE are
-    scaled (read + write of `gib` GiB per launch)."""
+    """Achievable HBM ceiling: the library's plain HIP copy kernel
+    (mf_stream_copy) moving `gib` GiB (one read + one write per byte, like the
+    step's algorithmic traffic) in each of its variants and three grid sizes,
+    the best of which is the ceiling; torch's copy_ of the same buffers beside
+    it.  The same copy is the reference against which rocprofv3's FETCH_SIZE
+    and WRITE_SIZE are scaled."""
     import torch
+    from paper_1905_05727_amd import meso
     n = int(gib * 2 ** 30) // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    b.copy_(a)
+    nbytes = n * 8
+    st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(reps):
+            f()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    kernels = {}
+    for variant, name in ((0, "x1"), (1, "x4"), (2, "x1_nt"), (3, "x4_nt")):
+        for wg in (0, 4096, 16384):
+            ms = timed(lambda: meso.stream_copy(a.data_ptr(), b.data_ptr(), nbytes, variant, wg,
+                                                st.cuda_stream))
+            kernels[f"{name}_wg{wg or 'auto'}"] = 2 * nbytes / (ms * 1e-3) / 1e9
+    assert torch.equal(a, b), "stream copy result differs from its source"
+    ms_torch = timed(lambda: b.copy_(a))
+    best = max(kernels, key=kernels.get)
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_per_launch": 2 * n * 8, "ms": ms, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+    return {"bytes_per_launch": 2 * nbytes, "GBs": kernels[best], "best": best,
+            "kernels_GBs": kernels, "torch_copy_GBs": 2 * nbytes / (ms_torch * 1e-3) / 1e9}
 
 
 def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
@@ -308,7 +340,7 @@ def liquids_bench(modes, steps, warmup, cpu_steps):
             v = valu_per_cell_from_profiles(name, m)
             if v is not None:
                 d["valu_per_cell"] = v
-                d["valu_issue_frac"] = v * N / (kms * 1e-3) / (ALU_PEAK_TOPS * 1e12)
+                d["valu_issue_frac"] = v * N / (kms * 1e-3) / (VALU_ISSUE_PEAK * 1e12)
             row["modes"][m] = d
             log(f"  {name} {m}: {d['value'] / 1e9:.2f} G cell-updates/s, kernel {kms:.3f} ms")
         if cpu_steps:
@@ -324,7 +356,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=8192, help="grid size (n x n)")
-    ap.add_argument("--modes", default="fp64,fp32_fp64acc,fp32")
+    ap.add_argument("--modes", default="fp64_fast,fp64,fp32_fp64acc,fp32")
+    ap.add_argument("--headline", default="fp64_fast",
+                    help="mode whose rate is the line's value (an FP64 mode: fp64_fast, fp64)")
+    ap.add_argument("--active-from", type=int, default=600,
+                    help="step from which a second window of each run is timed")
+    ap.add_argument("--active-steps", type=int, default=20,
+                    help="steps of that window (0: skip it)")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
@@ -363,45 +401,56 @@ def main():
     log(f"scenario {sc.name} {sc.nx}x{sc.ny}: {sc.meta['nbubbles']} bubbles, porosity "
         f"{sc.meta['porosity']:.3f} ({time.perf_counter() - t:.1f} s)")
     N = sc.nx * sc.ny
+    active = (args.active_from, args.active_steps) if args.active_steps > 0 else None
     res = {}
     for m in modes:
         log(f"mode {m}: warmup {args.warmup}, timing {args.steps} steps")
-        res[m] = run_mode(sc, m, args.steps, args.warmup, diagnostics=(m == "fp64"))
+        res[m] = run_mode(sc, m, args.steps, args.warmup, diagnostics=(m == "fp64"),
+                          active=active)
         r = res[m]
         log(f"  {N * args.steps / r['s'] / 1e9:.2f} G cell-updates/s, kernel "
-            f"{r['kernel_ms_avg']:.3f} ms/launch, t_sim {r['t_sim']:.3e}")
+            f"{r['kernel_ms_avg']:.3f} ms/launch, t_sim {r['t_sim']:.3e}"
+            + (f"; steps {r['active']['from_step']}+: kernel "
+               f"{r['active']['kernel_ms_avg']:.3f} ms" if "active" in r else ""))
+
+    cp = copy_bandwidth()
+    log(f"copy kernel: {cp['GBs']:.0f} GB/s ({cp['best']}; torch copy_ "
+        f"{cp['torch_copy_GBs']:.0f} GB/s; {cp['bytes_per_launch'] / 2 ** 30:.1f} GiB moved "
+        f"per launch)")
 
     mode_out = {}
     ref = res.get("fp64")
     for m, r in res.items():
         cups = N * args.steps / r["s"]
         ach = BYTES_PER_CELL[m] * N / (r["kernel_ms_avg"] * 1e-3) / 1e9
-        ops = OPS_PER_CELL * N / (r["kernel_ms_avg"] * 1e-3) / 1e12
         d = {"value": cups, "ms_per_step": 1e3 * r["s"] / args.steps,
              "kernel_ms": r["kernel_ms_avg"], "hbm_algorithmic_GBs": ach,
-             "hbm_frac": ach / HBM_PEAK_GBS, "alu_TOPs": ops, "alu_frac": ops / ALU_PEAK_TOPS,
+             "hbm_frac": ach / HBM_PEAK_GBS, "copy_ceiling_frac": ach / cp["GBs"],
              "dtype": DTYPE[m]}
+        if "active" in r:
+            a_ms = r["active"]["kernel_ms_avg"]
+            d["active_window"] = {
+                "from_step": r["active"]["from_step"], "steps": r["active"]["steps"],
+                "kernel_ms": a_ms,
+                "hbm_frac": BYTES_PER_CELL[m] * N / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         tb = traffic_from_profiles(m)
         if tb is not None:      # counted HBM bytes of the same kernel / its time here
             d["hbm_measured_GBs"] = tb / (r["kernel_ms_avg"] * 1e-3) / 1e9
             d["hbm_measured_frac"] = d["hbm_measured_GBs"] / HBM_PEAK_GBS
         cm = counters_from_profiles(m)
         if cm is not None and "SQ_INSTS_VALU" in cm:
-            # counted VALU instructions (one per wave, 64 lanes) of the same kernel / its time
-            # here, against the 4-cycle issue peak of 39.3 T lane-instructions/s
+            # counted VALU instructions (one per wave, 64 lanes) of the same kernel / its
+            # time here, against one wave64 instruction per SIMD every 4 cycles
             d["valu_per_cell"] = cm["SQ_INSTS_VALU"] * 64 / N
             d["valu_issue_frac"] = (cm["SQ_INSTS_VALU"] * 64 / (r["kernel_ms_avg"] * 1e-3)
-                                    / (ALU_PEAK_TOPS * 1e12))
+                                    / (VALU_ISSUE_PEAK * 1e12))
         if ref is not None and m != "fp64":
             for k in ("rho", "p"):
                 d[f"rel_l1_{k}_vs_fp64"] = float(np.abs(r["fields"][k] - ref["fields"][k]).sum()
                                                  / np.abs(ref["fields"][k]).sum())
         mode_out[m] = d
 
-    cp = copy_bandwidth()
-    log(f"device copy: {cp['GBs']:.0f} GB/s ({cp['bytes_per_launch'] / 2 ** 30:.1f} GiB moved "
-        f"per launch)")
-    head = "fp64" if "fp64" in res else modes[0]
+    head = args.headline if args.headline in res else modes[0]
     h = mode_out[head]
     r = res[head]
     line = {
@@ -423,18 +472,17 @@ def main():
                                f"seed {sc.meta['seed']}",
                    "cells": N, "precision": head, "parallelism": "single GPU",
                    "launch": r["launch"]},
-        "roofline": {"bound": "alu", "achieved": h["alu_TOPs"], "peak": ALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": h["alu_frac"],
+        "roofline": {"bound": "hbm", "achieved": h["hbm_algorithmic_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": h["hbm_frac"],
                      "traffic": traffic_from_profiles(head),
-                     "kernel": "step_kernel (fused x/y sweep)",
-                     "ops_per_cell": OPS_PER_CELL,
+                     "kernel": f"step_kernel ({head}, fused x/y sweep)",
+                     "bytes_per_cell": BYTES_PER_CELL[head], "cells_per_launch": N,
+                     "kernel_ms": h["kernel_ms"],
+                     "copy_ceiling_GBs": cp["GBs"], "copy_ceiling_frac": h["copy_ceiling_frac"],
                      "valu_issue": {"instr_per_cell": h.get("valu_per_cell"),
-                                    "frac": h.get("valu_issue_frac")},
-                     "hbm": {"achieved_GBs": h["hbm_algorithmic_GBs"], "peak_GBs": HBM_PEAK_GBS,
-                             "frac": h["hbm_frac"], "bytes_per_cell": BYTES_PER_CELL[head],
-                             "measured_GBs": h.get("hbm_measured_GBs"),
-                             "copy_kernel_GBs": cp["GBs"]}},
+                                    "frac": h.get("valu_issue_frac")}},
         "modes": mode_out,
+        "copy_kernel": cp,
     }
     if not args.no_serving:
         line["serving"] = serving_bench(args.serving_requests, args.serving_steps)

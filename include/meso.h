@@ -34,10 +34,11 @@
  *    progress lambda (primitive; the liquid's unreacted mass fraction, 1 =
  *    fresh) and the reactant mass z2 rho2 lambda (conserved).
  *  - Stepping calls only enqueue work on the solver's stream and return;
- *    errors found on the device (non-finite state, rho <= 0, rho c^2 <= 0)
- *    are latched and reported by the next synchronising call
- *    (mf_sync, mf_read_*, mf_get_time, mf_run_to_time) as
- *    MF_E_NONFINITE_STATE.  After such an error the state is unspecified;
+ *    errors found on the device (non-finite state, rho <= 0, rho c^2 <= 0;
+ *    a given time step above the CFL bound) are latched and reported by the
+ *    next synchronising call (mf_sync, mf_read_*, mf_get_time,
+ *    mf_run_to_time, the diagnostics) as MF_E_NONFINITE_STATE or
+ *    MF_E_CFL_VIOLATION.  After such an error the state is unspecified;
  *    the solver may be re-set (mf_set_*) or destroyed.
  *  - One solver is used from one host thread at a time.
  */
@@ -56,6 +57,7 @@ extern "C" {
 #define MF_E_INVALID_ARG     -1   /* bad argument; nothing was changed      */
 #define MF_E_OUT_OF_MEMORY   -2   /* device allocation or workspace too small */
 #define MF_E_NONFINITE_STATE -3   /* NaN/Inf, rho <= 0 or rho c^2 <= 0 found */
+#define MF_E_CFL_VIOLATION   -4   /* a given dt exceeded cfl / s_max          */
 #define MF_E_DEVICE          -5   /* HIP runtime error (launch, copy, sync)  */
 #define MF_E_NOT_READY       -6   /* result asked for before it exists       */
 #define MF_E_BUSY            -7   /* server has no free slot or budget       */
@@ -65,6 +67,12 @@ extern "C" {
 #define MF_FP32_FP64ACC  1  /* FP64 state, pressure inversion and update;
                                FP32 reconstruction, predictor and HLLC         */
 #define MF_FP32          2  /* FP32 state and arithmetic                       */
+#define MF_FP64_FAST     3  /* FP64 state and arithmetic with fused multiply-adds;
+                               divisions and square roots from the hardware
+                               reciprocal / reciprocal-square-root seeds refined
+                               by Newton steps (a few ulp each): within 1e-12
+                               relative L1 of the FP64 contract per field after
+                               the fixed step counts, not bit for bit          */
 
 /* Boundary conditions (Sec. 2.4, Fig. 1): transmissive = zero-order
  * extrapolation of the edge cell; periodic = wrap (must be set on both
@@ -179,9 +187,13 @@ int32_t mf_set_conserved(mf_solver *s, const double *cons);
  * x then y on even steps, y then x on odd steps).  Synchronises. */
 int32_t mf_set_time(mf_solver *s, double t, int64_t step);
 
-/* Enqueue one step.  dt > 0: use this time step; dt <= 0: dt = CFL / max
- * signal speed of the current state (computed on the device; no host round
- * trip).  Does not synchronise. */
+/* Enqueue one step.  dt <= 0: dt = CFL / max signal speed of the current
+ * state (computed on the device; no host round trip).  dt > 0: use this time
+ * step, which must not exceed that bound (the solver's cfl over the signal
+ * speed bound s_max = max over cells of max((|u| + c)/dx, (|v| + c)/dy));
+ * a larger dt is not taken: the step and every later one are skipped and the
+ * next synchronising call reports MF_E_CFL_VIOLATION (found on the device, so
+ * this call still returns MF_OK).  Does not synchronise. */
 int32_t mf_step(mf_solver *s, double dt);
 
 /* Enqueue nsteps CFL steps (nsteps >= 0).  Does not synchronise. */
@@ -235,6 +247,17 @@ int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int3
  * the last reset (enable resets).  Costs two event records per launch. */
 int32_t mf_enable_timing(mf_solver *s, int32_t enable);
 int32_t mf_kernel_time(mf_solver *s, double *total_ms, int64_t *launches);
+
+/* Measurement reference: copy `bytes` bytes from src to dst (device
+ * pointers, 16-byte aligned, not overlapping; owned by the caller) with a
+ * plain HIP kernel on hip_stream (NULL = the null stream), one read and one
+ * write per byte like the algorithmic traffic of a step.  variant 0-3: 1 or 4
+ * 16-byte vectors per thread per trip (bit 0), ordinary or non-temporal
+ * loads and stores (bit 1); workgroups: grid size (0 = 8 per compute unit).
+ * Enqueues only.  MF_E_INVALID_ARG for NULL or misaligned pointers or a bad
+ * variant, MF_E_DEVICE if the launch fails. */
+int32_t mf_stream_copy(const void *src, void *dst, size_t bytes, int32_t variant,
+                       int32_t workgroups, void *hip_stream);
 
 /* Kernel launch geometry of the state-update kernel for this solver:
  * workgroups, threads per workgroup, and the number of cells one leading

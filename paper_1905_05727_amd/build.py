@@ -1,10 +1,10 @@
 """Build step of the HIP library (hipcc, gfx950).
 
-The shared library libmeso.so is built in-tree next to this file from six
+The shared library libmeso.so is built in-tree next to this file from eight
 translation units, compiled in parallel.  The FP64 kernels and the host code
 are compiled with -ffp-contract=off (every operation rounds separately, so
 the FP64 mode follows the arithmetic contract bit for bit); the FP32-bulk /
-FP32 kernels with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
+FP32 and fast-FP64 kernels with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
 packed FP32 instructions are disabled (-packed-fp32-ops).
 """
 from __future__ import annotations
@@ -28,6 +28,8 @@ ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 UNITS = [("meso_kernels.hip", "off", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
          ("meso_kernels_fast.hip", "fast", []),
          ("meso_kernels_react.hip", "off", []), ("meso_kernels_react_fast.hip", "fast", []),
+         ("meso_kernels_fast64.hip", "fast", []),
+         ("meso_stream.hip", "off", []),
          ("meso_api.hip", "off", []), ("meso_server.hip", "off", [])]
 
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fno-fast-math",

@@ -67,7 +67,7 @@ bool valid_scheme(const mf_options *opt) {
     if (!(opt->cfl > 0.0) || !(opt->cfl <= 1.0)) return false;
     if (!(opt->z_floor >= 0.0) || !(opt->z_floor < 0.5)) return false;
     if (opt->limiter != MF_LIM_VANLEER && opt->limiter != MF_LIM_MINMOD) return false;
-    if (opt->precision < MF_FP64 || opt->precision > MF_FP32) return false;
+    if (opt->precision < MF_FP64 || opt->precision > MF_FP64_FAST) return false;
     return true;
 }
 
@@ -260,6 +260,12 @@ namespace {
 
 int32_t dev_err(hipError_t e) { return e == hipSuccess ? MF_OK : MF_E_DEVICE; }
 
+// Status of the latched device error bits (0 = none).
+int32_t err_status(int err) {
+    if (err & 2) return MF_E_CFL_VIOLATION;
+    return err ? MF_E_NONFINITE_STATE : MF_OK;
+}
+
 // Index of the state copy that holds the state after `step` completed steps.
 int state_index(const mf_solver *s, long long step) {
     return s->opt.fused ? (int)(step & 1) : 0;
@@ -323,7 +329,7 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
 extern "C" {
 
 size_t mf_workspace_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision) {
-    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
+    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP64_FAST) return 0;
     if (mat && !meso::valid_materials(mat)) return 0;
     return kAlign + 2 * state_bytes(grid, precision, meso::planes_of(mat));
 }
@@ -436,7 +442,7 @@ int32_t mf_run_to_time(mf_solver *s, double t_end, int64_t max_steps, int64_t *s
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    if (c.err) return MF_E_NONFINITE_STATE;
+    if (c.err) return err_status(c.err);
     const long long start = c.step;
     long long chunk = 8;
     while (c.t < t_end && c.step - start < max_steps) {
@@ -452,7 +458,7 @@ int32_t mf_run_to_time(mf_solver *s, double t_end, int64_t max_steps, int64_t *s
         if (chunk < 256) chunk *= 2;
     }
     if (steps_taken) *steps_taken = c.step - start;
-    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+    return err_status(c.err);
 }
 
 int32_t mf_sync(mf_solver *s) {
@@ -460,7 +466,7 @@ int32_t mf_sync(mf_solver *s) {
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+    return err_status(c.err);
 }
 
 int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t count) {
@@ -472,7 +478,7 @@ int32_t mf_read_field(mf_solver *s, int32_t field, double *host_out, size_t coun
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    if (c.err) return MF_E_NONFINITE_STATE;
+    if (c.err) return err_status(c.err);
     double *tmp = nullptr;
     if (hipMalloc(&tmp, n * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
@@ -504,7 +510,7 @@ static int32_t column_pass(mf_solver *s, double **cols_out) {
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    if (c.err) return MF_E_NONFINITE_STATE;
+    if (c.err) return err_status(c.err);
     double *cols = nullptr;
     if (hipMalloc(&cols, sizeof(double) * ((3 + (size_t)s->d.nc) * s->grid.nx + 8)) !=
         hipSuccess) {
@@ -559,7 +565,7 @@ int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int3
     Control c;
     int32_t st = read_control(s, &c);
     if (st != MF_OK) return st;
-    if (c.err) return MF_E_NONFINITE_STATE;
+    if (c.err) return err_status(c.err);
     std::vector<double> edges(nbins + 1);
     for (int32_t k = 0; k <= nbins; ++k) edges[k] = pow(10.0, lo + (double)k * dn);
     double *dev = nullptr;
@@ -587,7 +593,7 @@ int32_t mf_get_time(mf_solver *s, double *t, int64_t *step, double *last_dt) {
     if (t) *t = c.t;
     if (step) *step = c.step;
     if (last_dt) *last_dt = c.dt;
-    return c.err ? MF_E_NONFINITE_STATE : MF_OK;
+    return err_status(c.err);
 }
 
 int32_t mf_enable_timing(mf_solver *s, int32_t enable) {
@@ -641,6 +647,7 @@ const char *mf_status_str(int32_t status) {
         case MF_E_INVALID_ARG: return "invalid argument";
         case MF_E_OUT_OF_MEMORY: return "out of device memory";
         case MF_E_NONFINITE_STATE: return "non-finite or non-physical state";
+        case MF_E_CFL_VIOLATION: return "time step above the CFL bound of the state";
         case MF_E_DEVICE: return "HIP runtime error";
         case MF_E_NOT_READY: return "not ready";
         case MF_E_BUSY: return "busy";

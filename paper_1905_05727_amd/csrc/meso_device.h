@@ -50,15 +50,19 @@
 namespace meso {
 
 // ------------------------------------------------------------------------
-// Arithmetic policies.  Ar<double, false>: IEEE division and square root (the
-// FP64 mode, bit-compatible with the arithmetic contract; the two powers of
-// the Cochran-Chan reference curves share one logarithm, v^-C = exp(-C ln v),
-// a few ulp from a correctly rounded pow).  Ar<double, true>:
-// hardware reciprocal refined by one Newton step and the hardware square
-// root (the FP64 closure of the FP32-bulk mode).  Ar<float, *>: hardware
-// reciprocal and square root.
-template <class T, bool FAST> struct Ar;
-template <> struct Ar<double, false> {
+// Arithmetic policies, by level FAST.  Ar<double, 0>: IEEE division and
+// square root (the FP64 mode, bit-compatible with the arithmetic contract; the
+// two powers of the Cochran-Chan reference curves share one logarithm,
+// v^-C = exp(-C ln v), a few ulp from a correctly rounded pow).
+// Ar<double, 1>: hardware reciprocal refined by one Newton step and the
+// hardware square root (the FP64 closure of the FP32-bulk mode).
+// Ar<double, 2>: the fast FP64 mode -- reciprocal and reciprocal square root
+// from the hardware seeds (about 23 correct bits) refined by two Newton steps,
+// quotients finished with one residual correction, so every result is within
+// a few ulp of the correctly rounded one at about half the instructions of
+// the IEEE sequences.  Ar<float, *>: hardware reciprocal and square root.
+template <class T, int FAST> struct Ar;
+template <> struct Ar<double, 0> {
     // v^-C and v^-D of the Cochran-Chan reference curves
     static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
                                               double &vd) {
@@ -72,7 +76,7 @@ template <> struct Ar<double, false> {
     static __device__ __forceinline__ double big() { return 1.0e300; }
     static __device__ __forceinline__ double ex(double a) { return exp(a); }
 };
-template <> struct Ar<double, true> {
+template <> struct Ar<double, 1> {
     static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
                                               double &vd) {
         const double l = log(v);
@@ -90,7 +94,45 @@ template <> struct Ar<double, true> {
     static __device__ __forceinline__ double big() { return 1.0e300; }
     static __device__ __forceinline__ double ex(double a) { return exp(a); }
 };
-template <bool FAST> struct Ar<float, FAST> {
+template <> struct Ar<double, 2> {
+    static __device__ __forceinline__ void pw(double v, double C, double D, double &vc,
+                                              double &vd) {
+        const double l = log(v);
+        vc = exp(-C * l);
+        vd = exp(-D * l);
+    }
+    // 1/a: seed r0 (relative error e0), r1 = r0 + r0 (1 - a r0) (error e0^2),
+    // r2 likewise (below one ulp)
+    static __device__ __forceinline__ double rcp(double a) {
+        double r = __builtin_amdgcn_rcp(a);
+        r = __builtin_fma(r, __builtin_fma(-a, r, 1.0), r);
+        return __builtin_fma(r, __builtin_fma(-a, r, 1.0), r);
+    }
+    // a/b: one Newton step on the seed, then the quotient q = a r1 corrected by
+    // its residual a - b q
+    static __device__ __forceinline__ double div(double a, double b) {
+        double r = __builtin_amdgcn_rcp(b);
+        r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+        const double q = a * r;
+        return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+    }
+    // 1/sqrt(a): y <- y + (y/2)(1 - a y^2), twice
+    static __device__ __forceinline__ double rsq(double a) {
+        double y = __builtin_amdgcn_rsq(a);
+        y = __builtin_fma(0.5 * y, __builtin_fma(-a * y, y, 1.0), y);
+        return __builtin_fma(0.5 * y, __builtin_fma(-a * y, y, 1.0), y);
+    }
+    // sqrt(a) = a / sqrt(a), corrected by the residual a - s^2.  For a > 0
+    // and finite only (0 gives NaN): the callers flag a non-positive a anyway
+    static __device__ __forceinline__ double sqrt_(double a) {
+        const double y = rsq(a);
+        const double s = a * y;
+        return __builtin_fma(__builtin_fma(-s, s, a), 0.5 * y, s);
+    }
+    static __device__ __forceinline__ double big() { return 1.0e300; }
+    static __device__ __forceinline__ double ex(double a) { return exp(a); }
+};
+template <int FAST> struct Ar<float, FAST> {
     static __device__ __forceinline__ void pw(float v, float C, float D, float &vc, float &vd) {
         const float l = __builtin_amdgcn_logf(v);        // log2 v
         vc = __builtin_amdgcn_exp2f(-C * l);
@@ -144,7 +186,7 @@ template <class T> __device__ __forceinline__ Rx<T> rx_of(const Desc &d) {
 // eta2 = z2 phi(rho2) and psi2 = z2 rho2 phi'(rho2), the term the density
 // dependence of phi adds to the frozen sound speed
 // rho c^2 = (p (1 + xi) + eta - psi) / xi.
-template <class T, bool FAST>
+template <class T, int FAST>
 __device__ __forceinline__ void liquid_terms(const Mix<T> &m, T a2, T z2, T &eta2, T &psi2) {
     const T rho2 = Ar<T, FAST>::div(a2, z2);
     const T v = Ar<T, FAST>::div(m.rho0, rho2);
@@ -174,7 +216,7 @@ template <int EOS, class T> __device__ __forceinline__ bool is_cc(const Mix<T> &
     return EOS < 0 ? m.eos2 == 1 : EOS == 1;
 }
 
-template <class S, bool FAST, int NC, int EOS = -1>
+template <class S, int FAST, int NC, int EOS = -1>
 __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w[NC], S &r,
                                              S &rc2) {
     const S rho = q[0] + q[1];
@@ -214,7 +256,7 @@ __device__ __forceinline__ void cons_to_prim(const Mix<S> &m, const S q[NC], S w
 // no lane needs it (a region at rest or a uniform state) skips it; the FP64
 // kernel stays branch-free, which keeps its six independent IEEE divisions
 // interleaved (it is latency bound at 2 waves per SIMD).
-template <class R, bool FAST, int LIM>
+template <class R, int FAST, int LIM>
 __device__ __forceinline__ R limit(R a, R b) {
     const R ab = a * b;
     if (LIM == 1) {
@@ -234,7 +276,7 @@ __device__ __forceinline__ R limit(R a, R b) {
 }
 
 // MUSCL reconstruction and Hancock half step in primitive variables.
-template <class R, bool FAST, int LIM, int NC>
+template <class R, int FAST, int LIM, int NC>
 __device__ __forceinline__ void face_states(const R wm[NC], const R w0[NC], const R wp[NC], R r,
                                             R rc2, R hl, R wl[NC], R wh[NC]) {
     R d[NC], s[NC];
@@ -262,7 +304,7 @@ template <class R, int NC> struct Side {
     R U[NC - 1], F[NC - 1];
 };
 
-template <class R, bool FAST, int NC, int EOS>
+template <class R, int FAST, int NC, int EOS>
 __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[NC], Side<R, NC> &s,
                                           R &c) {
     const R rho = w[0] + w[1];
@@ -296,7 +338,7 @@ __device__ __forceinline__ void side_eval(const Mix<R> &m, const R w[NC], Side<R
     }
 }
 
-template <class R, bool FAST, int NC>
+template <class R, int FAST, int NC>
 __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out[NC + 1]) {
     const R d = S - k.un;
     R chi;
@@ -324,7 +366,7 @@ __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out
 // NC = 7, the reactant-mass flux.  The star state is evaluated once, for the
 // side the contact moves away from; faces with S* == 0 exactly (or NaN)
 // evaluate both sides and average instead.
-template <class R, bool FAST, int NC, int EOS>
+template <class R, int FAST, int NC, int EOS>
 __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR[NC],
                                      R out[NC + 1]) {
     Side<R, NC> L, Rs;
@@ -342,7 +384,7 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     // the same star side also evaluates that side without selecting its
     // values per lane (same values; in the other kernels that second path
     // would cost occupancy)
-    constexpr bool kUniform = !FAST && EOS == 0;
+    constexpr bool kUniform = sizeof(R) == 8 && FAST != 1 && EOS == 0;
     R st[NC + 1];
     if (Ss > R(0) || Ss < R(0)) {
         const bool useL = Ss > R(0);
@@ -409,7 +451,7 @@ __device__ __forceinline__ void update_cell(const S q[NC], const R flo[NC + 1],
 // x sweep of one row of the strip.  All 256 threads call it (it holds
 // barriers); q: this thread's cell, qo: updated cell (valid for threads
 // 2..253; the halo threads return q unchanged).
-template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+template <class S, class R, int FAST, int LIM, int NC, int EOS>
 __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R hl,
                                       const Mix<S> &ms, const Mix<R> &mr,
                                       R (*sWF)[kThreads], R (*sH)[kThreads]) {
@@ -460,7 +502,7 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
 // x_row for the batched kernel: idle (uniform per wave) means the wave lies
 // wholly right of the grid's last halo column, so nothing that is stored
 // depends on it; it only takes part in the barriers.
-template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+template <class S, class R, int FAST, int LIM, int NC, int EOS>
 __device__ __forceinline__ void x_row_skip(const S q[NC], S qo[NC], int t, S lam, R hl,
                                       const Mix<S> &ms, const Mix<R> &mr,
                                       R (*sWF)[kThreads], R (*sH)[kThreads], bool idle) {
@@ -513,7 +555,7 @@ __device__ __forceinline__ void x_row_skip(const S q[NC], S qo[NC], int t, S lam
 // y sweep as a rolling window down one column (registers only).  Rows are
 // pushed in order; after the 5th row the window yields the updated row two
 // behind the one pushed.  Values are in the y frame (normal momentum rho v).
-template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+template <class S, class R, int FAST, int LIM, int NC, int EOS>
 struct YPipe {
     S q1[NC], q2[NC];    // conserved rows k-1, k-2
     R w1[NC], w2[NC];    // primitives rows k-1, k-2
@@ -569,7 +611,7 @@ template <class S, int NC> __device__ __forceinline__ void to_yframe(const S a[N
 // exp(-C exp(-Ta / T2) h); the reacted liquid mass releases Q per unit mass
 // into rho E (source of Eq. (1)).  Cells without reactant or with T2 <= 0
 // are left as they are.
-template <class S, bool FAST>
+template <class S, int FAST>
 __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S h) {
     if (!(q[6] > S(0))) return;
     S w[7], r, rc2;
@@ -589,7 +631,7 @@ __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S
 
 // Pointwise stage and CFL contribution of one updated cell (U order): the z1
 // clamp, the second half of the reaction (NC = 7), then the signal speed.
-template <class S, bool FAST, int NC, int EOS>
+template <class S, int FAST, int NC, int EOS>
 __device__ __forceinline__ void epilogue(S q[NC], const Mix<S> &ms, const Rx<S> &rx, S hdt,
                                          S zlo, S zhi, S idx, S idy, S &smax, int &bad) {
     q[5] = fmin(fmax(q[5], zlo), zhi);
@@ -639,7 +681,7 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // of two sweeps) applies the first half of the reaction stage (NC = 7) to
 // every value it loads, halo cells included.  All threads of the workgroup
 // call it.
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS,
+template <class S, class R, int FAST, int LIM, int MODE, bool FINAL, int NC, int EOS,
           bool SKIP = false>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
                                          R (*sWF)[kThreads], R (*sH)[kThreads]) {
@@ -773,7 +815,7 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
 #endif
 
 // State update of one solve: grid (strips, segments).
-template <class S, class R, bool FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
+template <class S, class R, int FAST, int LIM, int MODE, bool FINAL, int NC, int EOS>
 __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void step_kernel(Desc d, int src_idx) {
     __shared__ R sWF[NC + 1][kThreads];
     __shared__ R sH[NC][kThreads];
@@ -787,7 +829,7 @@ __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void step_kernel(Desc d, i
 // launch has the same liquid EOS and number of conserved planes NC (the server
 // launches one of these per class present); waves beyond a small grid's last
 // halo column skip their arithmetic (SKIP).
-template <class S, class R, bool FAST, int LIM, int EOS, int NC>
+template <class S, class R, int FAST, int LIM, int EOS, int NC>
 __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void batched_step_kernel(const Desc *descs,
                                                                                const int4 *tiles) {
     __shared__ R sWF[NC + 1][kThreads];
@@ -802,7 +844,7 @@ __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void batched_step_kernel(c
 
 // The batched kernel for one class of solves: an inert liquid with EoS eos
 // (NC = 6), or the reactive Cochran-Chan liquid (NC = 7).
-template <class S, class R, bool FAST, int NC>
+template <class S, class R, int FAST, int NC>
 auto batched_variant(int lim, int eos) -> void (*)(const Desc *, const int4 *) {
     if constexpr (NC == 7) {
         return lim == 1 ? batched_step_kernel<S, R, FAST, 1, 1, 7>
@@ -816,7 +858,7 @@ auto batched_variant(int lim, int eos) -> void (*)(const Desc *, const int4 *) {
     }
 }
 
-template <class S, class R, bool FAST, int NC>
+template <class S, class R, int FAST, int NC>
 void launch_batched_variants(const Desc *descs, const int4 *tiles, int ntiles, int lim, int eos,
                              hipStream_t st) {
     void (*k)(const Desc *, const int4 *) = batched_variant<S, R, FAST, NC>(lim, eos);
@@ -825,7 +867,7 @@ void launch_batched_variants(const Desc *descs, const int4 *tiles, int ntiles, i
 
 // Host-side launch of the step kernel variant for one sweep mode (kXY, kYX,
 // or a single sweep kX / kY that does or does not end the step).
-template <class S, class R, bool FAST, int LIM, int NC, int EOS>
+template <class S, class R, int FAST, int LIM, int NC, int EOS>
 void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
     void (*k)(Desc, int);
@@ -845,7 +887,7 @@ void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, 
 }
 
 // Liquid chosen from the descriptor: a reactive solve is always Cochran-Chan.
-template <class S, class R, bool FAST, int LIM, int NC>
+template <class S, class R, int FAST, int LIM, int NC>
 void launch_step_variants(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     if constexpr (NC == 7) {
         launch_step_variants_eos<S, R, FAST, LIM, 7, 1>(d, mode, final_pass, src, st);

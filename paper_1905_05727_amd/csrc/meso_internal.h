@@ -19,8 +19,9 @@ constexpr int kTileW = kThreads - 2 * kHalo;
 // Largest y dimension of a launch grid: the segments of one strip.
 constexpr int kMaxSegs = 65535;
 
-// Precision modes (same numbering as MF_FP64 / MF_FP32_FP64ACC / MF_FP32).
-enum { kP64 = 0, kPMix = 1, kP32 = 2 };
+// Precision modes (same numbering as MF_FP64 / MF_FP32_FP64ACC / MF_FP32 /
+// MF_FP64_FAST).
+enum { kP64 = 0, kPMix = 1, kP32 = 2, kP64F = 3 };
 // Step kernel variants: fused x-then-y, fused y-then-x, single x sweep,
 // single y sweep.
 enum { kXY = 0, kYX = 1, kX = 2, kY = 3 };
@@ -36,7 +37,7 @@ struct alignas(256) Control {
     long long step;          // completed steps
     long long step_exec;     // index of the step being executed
     int skip;                // 1: the enqueued step does nothing
-    int err;                 // latched error bits (1 = bad state)
+    int err;                 // latched error bits (1 = bad state, 2 = dt above the CFL bound)
 };
 
 // Everything a step kernel needs to know about one solve.
@@ -136,5 +137,10 @@ hipError_t launch_batched_step_react(const Desc *descs, const int4 *tiles, int n
                                      int lim, hipStream_t st);
 hipError_t launch_batched_step_react_fast(const Desc *descs, const int4 *tiles, int ntiles,
                                           int prec, int lim, hipStream_t st);
+// The fast FP64 mode, inert and reactive (meso_kernels_fast64.hip).
+hipError_t launch_step_fast64(const Desc &d, int lim, int mode, int final_pass, int src,
+                              hipStream_t st);
+hipError_t launch_batched_step_fast64(const Desc *descs, const int4 *tiles, int ntiles, int lim,
+                                      int eos, int nc, hipStream_t st);
 
 }  // namespace meso

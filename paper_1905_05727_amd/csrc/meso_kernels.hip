@@ -9,9 +9,11 @@ namespace meso {
 // ------------------------------------------------------------------------
 // Small kernels around the step.
 
-// Time step of the step about to run (one thread).  dt_fixed > 0 overrides the
-// CFL bound; t_end > 0 shortens the last step to land on t_end and turns later
-// steps into no-ops.
+// Time step of the step about to run (one thread).  dt_fixed > 0 replaces the
+// CFL bound cfl / s_max of the current state, but may not exceed it: a larger
+// one latches a CFL violation (error bit 2) and the step is not taken.  t_end
+// > 0 shortens the last step to land on t_end and turns later steps into
+// no-ops.
 __global__ void dt_kernel(Control *ctl, double cfl, double dx, double dy, double dt_fixed,
                           double t_end) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -20,17 +22,20 @@ __global__ void dt_kernel(Control *ctl, double cfl, double dx, double dy, double
         ctl->skip = 1;
         return;
     }
-    double dt;
+    const double smax = __longlong_as_double((long long)ctl->smax_bits[n & 1]);
+    if (!(smax > 0.0) || !(smax <= 1.0e300)) {
+        ctl->err |= 1;
+        ctl->skip = 1;
+        return;
+    }
+    double dt = cfl / smax;
     if (dt_fixed > 0.0) {
-        dt = dt_fixed;
-    } else {
-        const double smax = __longlong_as_double((long long)ctl->smax_bits[n & 1]);
-        if (!(smax > 0.0) || !(smax <= 1.0e300)) {
-            ctl->err |= 1;
+        if (dt_fixed > dt) {
+            ctl->err |= 2;
             ctl->skip = 1;
             return;
         }
-        dt = cfl / smax;
+        dt = dt_fixed;
     }
     const double t = ctl->t;
     double tn;
@@ -144,7 +149,7 @@ __global__ void cons_from_f64_kernel(Desc d, int dst_idx, const double *cons) {
 }
 
 // CFL maximum of a state (no pointwise stage), into the slot of the current step.
-template <class S, bool FAST>
+template <class S, int FAST>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, int slot) {
     const long long N = (long long)d.nx * d.ny;
     const S *src = (const S *)d.buf[src_idx];
@@ -487,6 +492,7 @@ hipError_t launch_dt(const Desc &d, double cfl, double dx, double dy, double dt_
 
 hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
                        hipStream_t st) {
+    if (prec == kP64F) return launch_step_fast64(d, lim, mode, final_pass, src, st);
     if (d.nc == 7) return launch_step_react(d, prec, lim, mode, final_pass, src, st);
     if (prec != kP64) return launch_step_fast(d, prec, lim, mode, final_pass, src, st);
     if (lim == 1) launch_step_variants<double, double, false, 1, 6>(d, mode, final_pass, src, st);
@@ -503,6 +509,7 @@ hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st) {
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
                                int lim, int eos, int nc, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
+    if (prec == kP64F) return launch_batched_step_fast64(descs, tiles, ntiles, lim, eos, nc, st);
     if (nc == 7) return launch_batched_step_react(descs, tiles, ntiles, prec, lim, st);
     if (prec != kP64) return launch_batched_step_fast(descs, tiles, ntiles, prec, lim, eos, st);
     launch_batched_variants<double, double, false, 6>(descs, tiles, ntiles, lim, eos, st);

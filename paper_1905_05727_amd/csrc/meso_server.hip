@@ -468,7 +468,7 @@ void count(const mf_server *s, int32_t *active, int32_t *queued) {
 extern "C" {
 
 size_t mf_server_request_bytes(const mf_grid *grid, const mf_material mat[2], int32_t precision) {
-    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP32) return 0;
+    if (!meso::valid_grid(grid) || precision < MF_FP64 || precision > MF_FP64_FAST) return 0;
     if (mat && !meso::valid_materials(mat)) return 0;
     return request_bytes(grid, precision, meso::planes_of(mat));
 }
@@ -477,7 +477,7 @@ int32_t mf_server_create(const mf_server_config *cfg, void *hip_stream, mf_serve
     if (!out) return MF_E_INVALID_ARG;
     *out = nullptr;
     if (!cfg || cfg->hbm_budget < meso::kAlign || cfg->max_slots < 1 || cfg->max_slots > 65536 ||
-        cfg->precision < MF_FP64 || cfg->precision > MF_FP32 ||
+        cfg->precision < MF_FP64 || cfg->precision > MF_FP64_FAST ||
         (cfg->limiter != MF_LIM_VANLEER && cfg->limiter != MF_LIM_MINMOD) ||
         cfg->max_inflight < 1 || cfg->max_inflight > 64)
         return MF_E_INVALID_ARG;

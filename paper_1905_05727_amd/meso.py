@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libmeso.so")
 
 MF_OK = 0
 STATUS = {0: "MF_OK", -1: "MF_E_INVALID_ARG", -2: "MF_E_OUT_OF_MEMORY",
-          -3: "MF_E_NONFINITE_STATE", -5: "MF_E_DEVICE", -6: "MF_E_NOT_READY", -7: "MF_E_BUSY"}
-PRECISION = {"fp64": 0, "fp32_fp64acc": 1, "mixed": 1, "fp32": 2}
+          -3: "MF_E_NONFINITE_STATE", -4: "MF_E_CFL_VIOLATION", -5: "MF_E_DEVICE",
+          -6: "MF_E_NOT_READY", -7: "MF_E_BUSY"}
+PRECISION = {"fp64": 0, "fp32_fp64acc": 1, "mixed": 1, "fp32": 2, "fp64_fast": 3}
 LIMITER = {"vanleer": 0, "minmod": 1}
 BC = {"transmissive": 0, "periodic": 1}
 FIELDS = {"z1rho1": 0, "z2rho2": 1, "rhou": 2, "rhov": 3, "rhoE": 4, "z1": 5,
@@ -35,7 +36,7 @@ EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conser
            "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
            "mf_server_poll", "mf_server_finished", "mf_server_result", "mf_server_drain",
            "mf_server_get_stats",
-           "mf_server_destroy"]
+           "mf_server_destroy", "mf_stream_copy"]
 
 
 class MesoError(RuntimeError):
@@ -155,6 +156,7 @@ def load_library():
         "mf_server_get_stats": (C.c_int32, [P, C.POINTER(ServerStats)]),
         "mf_server_destroy": (C.c_int32, [P]),
         "mf_version": (C.c_char_p, []),
+        "mf_stream_copy": (C.c_int32, [P, P, C.c_size_t, C.c_int32, C.c_int32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -171,6 +173,16 @@ def _chk(call: str, st: int) -> None:
 
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, variant: int = 3, workgroups: int = 0,
+                stream: int = 0) -> None:
+    """Enqueue the library's plain device copy of `nbytes` bytes (device
+    pointers, e.g. ``tensor.data_ptr()``) on `stream` (a hipStream_t handle,
+    e.g. ``torch.cuda.current_stream().cuda_stream``)."""
+    _chk("mf_stream_copy", load_library().mf_stream_copy(
+        C.c_void_p(src_ptr), C.c_void_p(dst_ptr), C.c_size_t(nbytes), int(variant),
+        int(workgroups), C.c_void_p(stream)))
 
 
 def make_grid(nx, ny, dx, dy, bc=("transmissive",) * 4) -> Grid:

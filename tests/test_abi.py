@@ -31,6 +31,7 @@ def test_status_strings_and_version():
     lib = meso.load_library()
     assert lib.mf_status_str(0) == b"ok"
     assert lib.mf_status_str(-3) == b"non-finite or non-physical state"
+    assert lib.mf_status_str(-4) == b"time step above the CFL bound of the state"
     assert lib.mf_version().startswith(b"meso")
 
 
@@ -46,7 +47,7 @@ def test_workspace_bytes():
     lib = meso.load_library()
     for nx, ny in ((1, 1), (1000, 1), (1024, 512), (8192, 8192)):
         pitch = (nx + 63) // 64 * 64
-        for prec, es in (("fp64", 8), ("fp32_fp64acc", 8), ("fp32", 4)):
+        for prec, es in (("fp64", 8), ("fp64_fast", 8), ("fp32_fp64acc", 8), ("fp32", 4)):
             for mats, nc in ((None, 6), (reactive_pair(), 7)):
                 state = (nc * pitch * ny * es + 255) // 256 * 256
                 assert meso.workspace_bytes(nx, ny, precision=prec, mats=mats) == 256 + 2 * state
@@ -109,7 +110,7 @@ def _create(grid=None, mats=None, opt=None, ws=None, ws_bytes=0):
     dict(opt=meso.Options(1.5, 1e-6, 0, 0, 1, 0)),
     dict(opt=meso.Options(0.4, 0.6, 0, 0, 1, 0)),
     dict(opt=meso.Options(0.4, 1e-6, 2, 0, 1, 0)),
-    dict(opt=meso.Options(0.4, 1e-6, 0, 3, 1, 0)),
+    dict(opt=meso.Options(0.4, 1e-6, 0, 4, 1, 0)),      # precision modes are 0-3
     dict(opt=meso.Options(0.4, 1e-6, 0, 0, 2, 0)),
     dict(ws=0x1000, ws_bytes=10),          # workspace too small
     dict(ws=0x1001, ws_bytes=1 << 40),     # misaligned workspace
@@ -144,3 +145,15 @@ def test_server_request_bytes():
     rb7 = (7 * 200 * 100 * 8 + 255) // 256 * 256
     assert inert == 256 + 2 * st6 + rb6 and react == 256 + 2 * st7 + rb7
     assert lib.mf_server_request_bytes(C.byref(g), None, 9) == 0
+
+
+def test_stream_copy_validates_arguments():
+    """The copy kernel's host checks run before any launch: NULL or
+    misaligned pointers and unknown variants are rejected, an empty copy is a
+    no-op."""
+    lib = meso.load_library()
+    assert lib.mf_stream_copy(None, None, 0, 0, 0, None) == 0
+    assert lib.mf_stream_copy(None, C.c_void_p(0x1000), 64, 0, 0, None) == -1
+    assert lib.mf_stream_copy(C.c_void_p(0x1008), C.c_void_p(0x2000), 64, 0, 0, None) == -1
+    assert lib.mf_stream_copy(C.c_void_p(0x1000), C.c_void_p(0x2000), 64, 4, 0, None) == -1
+    assert lib.mf_stream_copy(C.c_void_p(0x1000), C.c_void_p(0x2000), 64, 0, -1, None) == -1

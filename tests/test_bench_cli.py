@@ -78,6 +78,15 @@ def test_source_hash_ignores_comments_and_whitespace(tmp_path, monkeypatch):
 
 
 def test_bytes_per_cell_and_peaks():
-    assert bench.BYTES_PER_CELL == {"fp64": 96, "fp32_fp64acc": 96, "fp32": 48}
-    assert abs(bench.ALU_PEAK_TOPS - 39.3216) < 1e-9
+    # one read and one write of the 6-plane state per step: 2 x 6 x 8 B, 2 x 6 x 4 B in FP32
+    assert bench.BYTES_PER_CELL == {"fp64": 96, "fp64_fast": 96, "fp32_fp64acc": 96,
+                                    "fp32": 48}
+    assert abs(bench.VALU_ISSUE_PEAK - 39.3216) < 1e-9
     assert np.isclose(bench.HBM_PEAK_GBS, 8000.0)
+
+
+def test_headline_is_an_fp64_mode():
+    ap_defaults = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                                 capture_output=True, text=True, timeout=120).stdout
+    assert "--headline" in ap_defaults
+    assert bench.DTYPE["fp64_fast"] == "f64" and bench.DTYPE["fp64"] == "f64"

@@ -331,29 +331,41 @@ def test_fp64_roofline_8192_sampled(start):
 
 def test_reduced_precision_roofline_8192():
     """Full 8192^2 roofline workload in the benchmark's launch configuration,
-    FP32-bulk and pure FP32 against FP64 after 300 steps (relative L1: density
-    <= 1e-4, pressure <= 1e-3); then one FP32-bulk step from the FP64 state,
-    checked on sampled cells against the oracle's step with the same dt (each
-    conserved value within 1e-6 of its plane's magnitude -- 3e-8 measured: the
-    flux path is FP32, the state and its update FP64)."""
+    at its fixed 1000 steps: FP32-bulk and pure FP32 against FP64 (relative
+    L1: density <= 1e-4, pressure <= 1e-3), fast FP64 against FP64 (relative
+    L1 <= 1e-12 for density, pressure and every conserved plane; the FP64 run
+    equals the oracle bit for bit, tested on sampled cells of this workload);
+    then one FP32-bulk step from the FP64 state, checked on sampled cells
+    against the oracle's step with the same dt (each conserved value within
+    1e-6 of its plane's magnitude -- 3e-8 measured: the flux path is FP32, the
+    state and its update FP64)."""
     sc = S.roofline_8192()
-    nsteps = 300
-    say(f"case: roofline 8192x8192, {nsteps} steps, three precisions")
+    nsteps = sc.steps
+    assert nsteps == 1000
+    say(f"case: roofline 8192x8192, {nsteps} steps, four precisions")
     fields = {}
-    for prec in ("fp64", "fp32_fp64acc", "fp32"):
+    for prec in ("fp64", "fp64_fast", "fp32_fp64acc", "fp32"):
         with meso.Solver.from_scenario(sc, precision=prec) as s:
             s.run_steps(nsteps)
             fields[prec] = {k: s.read_field(k) for k in ("rho", "p")}
             if prec == "fp64":
                 U0 = s.read_conserved()
                 t0, n0, _ = s.time()
+            elif prec == "fp64_fast":
+                Uf = s.read_conserved()
         torch.cuda.empty_cache()
-    for prec in ("fp32_fp64acc", "fp32"):
+    for prec, g_rho, g_p in (("fp64_fast", 1e-12, 1e-12), ("fp32_fp64acc", 1e-4, 1e-3),
+                             ("fp32", 1e-4, 1e-3)):
         e_rho = rel_l1(fields[prec]["rho"], fields["fp64"]["rho"])
         e_p = rel_l1(fields[prec]["p"], fields["fp64"]["p"])
         say(f"{prec}: rel L1 rho {e_rho:.3e}  p {e_p:.3e}")
-        assert e_rho <= 1e-4 and e_p <= 1e-3
-    del fields
+        assert e_rho <= g_rho and e_p <= g_p
+    nrm = np.abs(U0).reshape(6, -1).sum(axis=1)
+    nrm[2] = nrm[3] = max(nrm[2], nrm[3])
+    e = np.abs(Uf - U0).reshape(6, -1).sum(axis=1) / nrm
+    say(f"fp64_fast conserved planes: rel L1 {e}")
+    assert np.all(e <= 1e-12)
+    del fields, Uf
     with meso.Solver.from_scenario(sc, precision="fp32_fp64acc") as s:
         s.set_conserved(U0)
         s.set_time(t0, n0)
@@ -625,6 +637,48 @@ def test_nonfinite_state_is_reported():
             assert s.time()[1] == 2
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp64_fast"])
+def test_explicit_dt_above_cfl_bound_is_reported(prec):
+    """An explicit dt is checked on the device against cfl / s_max of the
+    state it would advance (the oracle's CFL step of that state): the bound
+    itself is taken, twice the bound -- a violation that leaves the state
+    finite and every kernel running normally -- is not: the step is skipped,
+    later steps do nothing, and the next synchronising call reports
+    MF_E_CFL_VIOLATION until a new state is set."""
+    sc = bubble(128, 64)
+    say(f"case: explicit dt above the CFL bound, {prec}")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(3)
+        o.run(3)
+        U3 = s.read_conserved()
+        o.U[...] = U3
+        dt_cfl, _ = o.cfl_dt()
+        # FP64 computes the oracle's s_max bit for bit, so the bound itself is
+        # allowed; the fast mode's s_max may differ in the last bits
+        s.step(dt_cfl if prec == "fp64" else dt_cfl * (1.0 - 1e-12))
+        s.sync()
+        assert s.time()[1] == 4
+        U4 = s.read_conserved()
+        o.U[...] = U4
+        dt_cfl, _ = o.cfl_dt()
+        t4 = s.time()[0]
+        s.step(2.0 * dt_cfl)
+        with pytest.raises(meso.MesoError) as ei:
+            s.sync()
+        assert ei.value.status == -4
+        s.run_steps(2)
+        with pytest.raises(meso.MesoError) as ei:
+            s.time()
+        assert ei.value.status == -4
+        # a state set from the host clears the error
+        s.set_conserved(U4)
+        s.set_time(t4, 4)
+        s.run_steps(1)
+        s.sync()
+        assert s.time()[1] == 5
+
+
 # ------------------------------------------------------------ diagnostics ----
 @pytest.mark.parametrize("shape", [(300, 140), (40, 9), (33, 49)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32"])
@@ -651,3 +705,53 @@ def test_diagnostics_match_oracle(prec, shape):
     fo = o.log_histogram(9, 4.0, 0.02, 300, m_ref)
     assert np.array_equal(f > 0, fo > 0)
     np.testing.assert_allclose(f, fo, rtol=1e-12, atol=0)
+
+
+def roofline_crop(rows=256):
+    """The first `rows` rows of the 8192^2 roofline field (8192 x rows cells:
+    2.1 M at 256 rows, above the 4096 x 256 cells from which the histogram
+    kernel's threads take several cells each and step their coordinates with
+    the grid stride)."""
+    sc = S.roofline_8192()
+    sc.prim = np.ascontiguousarray(sc.prim[:, :rows, :])
+    sc.ny = rows
+    return sc
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64_fast", "fp32_fp64acc", "fp32"])
+def test_diagnostics_match_oracle_full_width(prec):
+    """The diagnostics on an 8192 x 256 crop of the roofline field after 200
+    steps (the shock has reached the first bubbles), in the launch
+    configuration every full-size call takes (more cells than histogram
+    threads, so each thread walks several cells with the stride carry; 33
+    column blocks with a ragged last one): averages and integrals bit for bit,
+    pressure and density PDFs with the same bin decisions, against the oracle
+    on the stored values.  A bin's mass is a sum of up to N positive cell
+    masses, which the oracle adds in sequence and the GPU in workgroup
+    partial sums and atomic adds: any two orders agree to 2 N u relative
+    (u = 2^-53), the bin masses' gate here."""
+    sc = roofline_crop()
+    say(f"case: diagnostics 8192x256 crop, {prec}")
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(200)
+        U = s.read_conserved()
+        pb, rb, ub = s.y_averages()
+        integ = s.integrals()
+        m_ref = float(U[1].sum() * sc.dx * sc.dy)
+        fp = s.log_histogram("p", 4.0, 0.015, 400, m_ref)
+        fr = s.log_histogram("rho", -1.0, 0.01, 400, m_ref)
+    o = oracle_of(sc)
+    o.U[...] = U
+    po, ro, uo = o.y_averages()
+    assert_bitwise(np.stack([pb, rb, ub]), np.stack([po, ro, uo]), "y averages 8192x256")
+    assert_bitwise(integ, o.integrals(), "integrals 8192x256")
+    rtol = 2.0 * sc.nx * sc.ny * 2.0 ** -53
+    for name, f, field, lo, dn in (("p", fp, 9, 4.0, 0.015), ("rho", fr, 6, -1.0, 0.01)):
+        fo = o.log_histogram(field, lo, dn, 400, m_ref)
+        nz = fo > 0
+        worst = float(np.max(np.abs(f[nz] - fo[nz]) / fo[nz]))
+        say(f"{name} PDF: {np.count_nonzero(fo)} bins occupied, largest relative bin "
+            f"difference {worst:.2e} (gate {rtol:.2e})")
+        assert np.count_nonzero(fo) > 5, name
+        assert np.array_equal(f > 0, nz), name
+        np.testing.assert_allclose(f, fo, rtol=rtol, atol=0, err_msg=name)

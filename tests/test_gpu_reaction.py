@@ -199,6 +199,36 @@ def test_reactive_diagnostics_match_oracle():
     assert f.sum() > 0.0
 
 
+def test_reactive_diagnostics_full_size_launch():
+    """The reacting cavity array of the paper cropped to 4800 x 313 cells
+    (1.5 M cells: the histogram kernel's threads walk several cells each with
+    the grid stride, as in every full-size call) after 60 steps: q-dot and
+    density PDFs and the reactant-mass integral against the oracle on the
+    stored values."""
+    sc = S.regular_array(liquid="nm", p_shock=7.81e9, reactive=True, length=4800)
+    assert sc.nx * sc.ny > 4096 * 256
+    say(f"case: reactive diagnostics {sc.nx}x{sc.ny}")
+    with meso.Solver.from_scenario(sc, precision="fp64") as s:
+        s.run_steps(60)
+        U = s.read_conserved()
+        I = s.integrals()
+        m_tot = float(I[1])
+        f = s.log_histogram("qdot", 2.0, 0.02, 400, m_tot)
+        fr = s.log_histogram("rho", 2.0, 0.02, 200, m_tot)
+    o = oracle_of(sc)
+    o.U[...] = U
+    assert np.allclose(I, o.integrals(), rtol=1e-12, atol=0)
+    fo = o.log_histogram(14, 2.0, 0.02, 400, m_tot)
+    fro = o.log_histogram(6, 2.0, 0.02, 200, m_tot)
+    assert np.array_equal(fr > 0, fro > 0)
+    # bin masses: sums of up to N cell masses in two orders, within 2 N u
+    assert np.allclose(fr, fro, rtol=2.0 * sc.nx * sc.ny * 2.0 ** -53, atol=0)
+    cell = float(U[1].max()) * sc.dx * sc.dy / m_tot / 0.02
+    say(f"q-dot PDF mass {f.sum() * 0.02:.4e} (oracle {fo.sum() * 0.02:.4e})")
+    assert f.sum() > 0.0
+    assert np.all(np.abs(np.cumsum(f) - np.cumsum(fo)) <= 2 * cell)
+
+
 def test_reactive_regular_array_paper_grid_sampled():
     """The paper's reactive regular-array workload (24000 x 313, 100 cells per
     cavity, periodic top/bottom, 7.81 GPa, shocked strip at lambda = 0): after
