@@ -233,6 +233,19 @@ int32_t mf_y_averages(mf_solver *s, double *p_bar, double *rho_bar, double *u_ba
  * and the remaining reactant mass M_2,r of Eq. (10). */
 int32_t mf_integrals(mf_solver *s, double *out, size_t count);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc / hipFree between steps): mf_integrals
+ * with the same arguments, results and errors, but its device scratch (the
+ * column sums and the integrals) is a fixed 4 MiB array in the library's
+ * device memory instead of a temporary allocation, so the call allocates
+ * nothing.  Limit: (3 + planes) * nx + planes <= 524288 doubles, i.e.
+ * nx <= 52428 with 7 planes (58253 with 6); a wider grid gives
+ * MF_E_INVALID_ARG.  Every call on one device shares that device's array:
+ * calls that overlap on one device (solvers driven from several host
+ * threads) race and must be serialised by the caller.  Synchronises the
+ * solver's stream. */
+int32_t mf_integrals_noalloc(mf_solver *s, double *out, size_t count);
+
 /* Mass-weighted probability density on log-spaced bins (Sec. 4.5): bin k
  * covers 10^(lo + k dn) <= v < 10^(lo + (k+1) dn) of the field v (MF_P,
  * MF_RHO, or MF_QDOT of a reactive solver), collects the liquid mass

@@ -12,6 +12,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -254,7 +255,53 @@ struct mf_solver {
     bool timing;
     std::vector<EventPair> ev;
     size_t ev_used;
+    int device;           // HIP device current at creation
 };
+
+// Scratch of mf_integrals_noalloc: the column sums ((3 + nc) * nx doubles)
+// followed by the nc integrals, in a file-scope device array (every device
+// the library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: it is a host-side stand-in for
+// the symbol, whose device address is looked up once per device.
+static constexpr size_t kScratchDoubles = size_t(1) << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[kMaxDevices];   // device address of `scratch` on each device
+
+// Device address of the scratch array on `device` (looked up on the first
+// call for that device, with that device current; the caller's current
+// device is restored).
+int32_t scratch_on(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return MF_E_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) {
+            (void)hipGetLastError();
+            return MF_E_DEVICE;
+        }
+        if (cur != device && hipSetDevice(device) != hipSuccess) {
+            (void)hipGetLastError();
+            return MF_E_DEVICE;
+        }
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return MF_E_DEVICE;
+        }
+        scratch_ptr[device] = (double *)p;
+    }
+    *out = scratch_ptr[device];
+    return MF_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -356,6 +403,11 @@ int32_t mf_create(const mf_grid *grid, const mf_material mat[2], const mf_option
     s->ws_bytes = need;
     s->timing = false;
     s->ev_used = 0;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return MF_E_DEVICE;
+    }
     if (s->own_ws) {
         if (hipMalloc(&s->ws, need) != hipSuccess) {
             (void)hipGetLastError();
@@ -552,6 +604,27 @@ int32_t mf_integrals(mf_solver *s, double *out, size_t count) {
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e == hipSuccess) e = hipMemcpy(out, res, count * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(cols);
+    return dev_err(e);
+}
+
+int32_t mf_integrals_noalloc(mf_solver *s, double *out, size_t count) {
+    if (!s || !out || count != (size_t)s->d.nc) return MF_E_INVALID_ARG;
+    const size_t ncols = (3 + (size_t)s->d.nc) * s->grid.nx;
+    if (ncols + count > kScratchDoubles) return MF_E_INVALID_ARG;
+    double *cols = nullptr;
+    int32_t st = scratch_on(s->device, &cols);
+    if (st != MF_OK) return st;
+    Control c;
+    st = read_control(s, &c);
+    if (st != MF_OK) return st;
+    if (c.err) return err_status(c.err);
+    // every value of both regions is written by the kernels below: nothing to clear
+    double *res = cols + ncols;
+    hipError_t e = meso::launch_columns(s->d, s->opt.precision, state_index(s, c.step), cols,
+                                        s->stream);
+    if (e == hipSuccess) e = meso::launch_integrals(s->d, cols, res, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(out, res, count * sizeof(double), hipMemcpyDeviceToHost);
     return dev_err(e);
 }
 

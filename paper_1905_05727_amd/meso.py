@@ -36,7 +36,7 @@ EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conser
            "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
            "mf_server_poll", "mf_server_finished", "mf_server_result", "mf_server_drain",
            "mf_server_get_stats",
-           "mf_server_destroy", "mf_stream_copy"]
+           "mf_server_destroy", "mf_stream_copy", "mf_integrals_noalloc"]
 
 
 class MesoError(RuntimeError):
@@ -138,6 +138,7 @@ def load_library():
         "mf_launch_info": (C.c_int32, [P, I64, I32, I32, I32]),
         "mf_y_averages": (C.c_int32, [P, D, D, D, C.c_size_t]),
         "mf_integrals": (C.c_int32, [P, D, C.c_size_t]),
+        "mf_integrals_noalloc": (C.c_int32, [P, D, C.c_size_t]),
         "mf_log_histogram": (C.c_int32, [P, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                          C.c_double, D]),
         "mf_destroy": (C.c_int32, [P]),
