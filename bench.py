@@ -143,6 +143,39 @@ def run_mode(sc, prec, steps, warmup, diagnostics=False, active=None):
     return out
 
 
+def time_recording(sc, prec, steps, warmup):
+    """Cost of the fused transverse averages (Sec. 4.2, an x-t row per step):
+    the same steps of the workload timed without and with recording -- state
+    kernel time by HIP events and wall time per step, which with recording
+    includes the small kernel that adds the segment sums into the row."""
+    import torch
+    from paper_1905_05727_amd import meso
+    out = {}
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(warmup)
+        s.sync()
+        rows = torch.empty((steps, 3, sc.nx), dtype=torch.float64, device="cuda")
+        for key, rec in (("plain", False), ("recording", True)):
+            if rec:
+                s.record_averages(rows.data_ptr(), steps)
+            s.enable_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run_steps(steps)
+            s.sync()
+            t1 = time.perf_counter()
+            kms, launches = s.kernel_time()
+            out[key] = {"step_kernel_ms": kms / max(launches, 1),
+                        "wall_ms_per_step": 1e3 * (t1 - t0) / steps}
+            s.record_averages(0, 0)
+        assert bool(torch.isfinite(rows).all())
+        del rows
+    out["extra_ms_per_step"] = (out["recording"]["wall_ms_per_step"]
+                                - out["plain"]["wall_ms_per_step"])
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(gib: float = 2.0, reps: int = 5):
     """Achievable HBM ceiling: the library's plain HIP copy kernel
     (mf_stream_copy) moving `gib` GiB (one read + one write per byte, like the
@@ -498,7 +531,14 @@ def main():
         # each diagnostic reads the whole FP64 state once (6 planes x 8 B per cell)
         nbytes = 48 * N
         g = res["fp64"]["diagnostics_ms"]
+        fused = {m: time_recording(sc, m, 20, args.warmup) for m in (head, "fp32_fp64acc")
+                 if m in res}
+        for m, f in fused.items():
+            log(f"fused averages {m}: step kernel {f['plain']['step_kernel_ms']:.3f} -> "
+                f"{f['recording']['step_kernel_ms']:.3f} ms, wall +{f['extra_ms_per_step']:.3f} "
+                f"ms per step (separate pass {g['y_averages']:.3f} ms)")
         line["diagnostics"] = {
+            "fused_averages": fused,
             "state": "FP64 roofline field after the timed steps", "bytes_read": nbytes,
             "gpu_ms": g, "gpu_GBs": {k: nbytes / (v * 1e-3) / 1e9 for k, v in g.items()},
             "gpu_hbm_frac": {k: nbytes / (v * 1e-3) / 1e9 / HBM_PEAK_GBS for k, v in g.items()},

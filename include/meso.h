@@ -254,6 +254,30 @@ int32_t mf_integrals_noalloc(mf_solver *s, double *out, size_t count);
 int32_t mf_log_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
                          double m_ref, double *f_out);
 
+/* Fused transverse averages (Sec. 4.2), for x-t diagrams at every step: while
+ * recording, each step also sums, per column, the pressure (FP64 closure of
+ * the stored values), the density and the x momentum of the state it stores
+ * -- in its store epilogue, so the state is not read a second time -- and
+ * writes one row of 3*nx doubles (p_bar, rho_bar, u_bar as in mf_y_averages)
+ * to dev_rows: row r (dev_rows + 3*nx*r) is the state after the r-th step
+ * enqueued since this call, or NaN for a step the device skipped (an error,
+ * or run-to-time at its end).  dev_rows: device memory of at least
+ * 3*nx*max_rows doubles, owned by the caller and kept alive while recording.
+ * After max_rows rows, steps are taken without recording; dev_rows = NULL
+ * stops recording.  Each column is summed segment by segment (the rows of a
+ * segment of the launch in increasing j, then the segments in increasing j),
+ * so a value may differ from mf_y_averages of the same state by up to 2 ny u
+ * of the sum of magnitudes (u = 2^-53), and depends on nothing but the grid
+ * and the launch geometry.  Fused solvers (mf_options.fused = 1) only; the
+ * first call allocates 3*nx*(segments) doubles of partial sums, freed by
+ * mf_destroy.  MF_E_INVALID_ARG (unfused solver, max_rows < 1, misaligned
+ * pointer), MF_E_OUT_OF_MEMORY.  Enqueues nothing itself. */
+int32_t mf_record_averages(mf_solver *s, double *dev_rows, int64_t max_rows);
+
+/* Rows enqueued since recording started (complete once the stream has run
+ * them, e.g. after mf_sync).  Does not synchronise. */
+int32_t mf_recorded_rows(mf_solver *s, int64_t *rows);
+
 /* Kernel timing: when enabled, every step kernel launch is bracketed by HIP
  * events on the solver's stream.  mf_kernel_time synchronises and returns the
  * summed duration (ms) and launch count of the state-update kernels since

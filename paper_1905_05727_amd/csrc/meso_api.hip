@@ -158,6 +158,7 @@ void set_segments(Desc &d, int ny, int h, int h2, int tail_rows) {
 void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,
                char *base, int seg_h) {
     d.ctl = (Control *)base;
+    d.diag = nullptr;
     d.buf[0] = base + kAlign;
     d.nc = planes_of(mat);
     d.buf[1] = base + kAlign + state_bytes(g, opt->precision, d.nc);
@@ -256,6 +257,11 @@ struct mf_solver {
     std::vector<EventPair> ev;
     size_t ev_used;
     int device;           // HIP device current at creation
+    // fused averages: segment sums (library-owned), the caller's rows, their
+    // number and the rows enqueued so far
+    double *rec_part;
+    double *rec_rows;
+    int64_t rec_max, rec_done;
 };
 
 // Scratch of mf_integrals_noalloc: the column sums ((3 + nc) * nx doubles)
@@ -354,8 +360,10 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
         ep = &s->ev[s->ev_used++];
         if (hipEventRecord(ep->a, s->stream) != hipSuccess) return MF_E_DEVICE;
     }
+    const bool rec = s->opt.fused && s->rec_rows && s->rec_done < s->rec_max;
     if (s->opt.fused) {
         const int src = (int)(n & 1);
+        if (rec) s->d.diag = s->rec_part;
         e = meso::launch_step(s->d, prec, lim, (n & 1) ? meso::kYX : meso::kXY, 1, src,
                               s->stream);
     } else {
@@ -365,8 +373,21 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
         e = meso::launch_step(s->d, prec, lim, first, 0, 0, s->stream);
         if (e == hipSuccess) e = meso::launch_step(s->d, prec, lim, second, 1, 1, s->stream);
     }
-    if (e != hipSuccess) return MF_E_DEVICE;
-    if (ep && hipEventRecord(ep->b, s->stream) != hipSuccess) return MF_E_DEVICE;
+    if (e != hipSuccess) {
+        s->d.diag = nullptr;
+        return MF_E_DEVICE;
+    }
+    if (ep && hipEventRecord(ep->b, s->stream) != hipSuccess) {
+        s->d.diag = nullptr;
+        return MF_E_DEVICE;
+    }
+    if (rec) {
+        e = meso::launch_diag_row(s->d, s->rec_rows + s->rec_done * 3 * (int64_t)s->grid.nx,
+                                  s->stream);
+        s->d.diag = nullptr;
+        if (e != hipSuccess) return MF_E_DEVICE;
+        ++s->rec_done;
+    }
     s->host_step = n + 1;
     return MF_OK;
 }
@@ -702,9 +723,38 @@ int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int3
     return MF_OK;
 }
 
+int32_t mf_record_averages(mf_solver *s, double *dev_rows, int64_t max_rows) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (!dev_rows) {   // stop recording; the rows written stay the caller's
+        s->rec_rows = nullptr;
+        return MF_OK;
+    }
+    if (!s->opt.fused || max_rows < 1 || ((uintptr_t)dev_rows % sizeof(double)) != 0)
+        return MF_E_INVALID_ARG;
+    if (!s->rec_part) {
+        const size_t n = 3 * (size_t)s->grid.nx * s->d.nsegs;
+        if (hipMalloc(&s->rec_part, n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->rec_part = nullptr;
+            return MF_E_OUT_OF_MEMORY;
+        }
+    }
+    s->rec_rows = dev_rows;
+    s->rec_max = max_rows;
+    s->rec_done = 0;
+    return MF_OK;
+}
+
+int32_t mf_recorded_rows(mf_solver *s, int64_t *rows) {
+    if (!s || !rows) return MF_E_INVALID_ARG;
+    *rows = s->rec_done;
+    return MF_OK;
+}
+
 int32_t mf_destroy(mf_solver *s) {
     if (!s) return MF_E_INVALID_ARG;
     hipError_t e = hipStreamSynchronize(s->stream);
+    if (s->rec_part) (void)hipFree(s->rec_part);
     for (auto &p : s->ev) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

@@ -33,7 +33,8 @@
 // rolling window held in registers (no exchange at all).  A fused step runs
 // both sweeps in one pass over the segment, so the state is read and written
 // once per step; the pointwise stage and the next step's CFL maximum are
-// computed in the epilogue from the values about to be stored.
+// computed in the epilogue from the values about to be stored, and a
+// recording step also sums the transverse averages of Sec. 4.2 there.
 //
 // Precision is a template parameter of the same code: S is the storage /
 // accumulation type, R the type of reconstruction, predictor and Riemann
@@ -682,7 +683,7 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // every value it loads, halo cells included.  All threads of the workgroup
 // call it.
 template <class S, class R, int FAST, int LIM, int MODE, bool FINAL, int NC, int EOS,
-          bool SKIP = false>
+          bool SKIP = false, bool DIAG = false>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
                                          R (*sWF)[kThreads], R (*sH)[kThreads]) {
     Control *ctl = d.ctl;
@@ -734,11 +735,24 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     auto start = [&](S q[NC]) {
         if constexpr (NC == 7 && kStarts) react<S, FAST>(q, ms, rx, hdt);
     };
+    // DIAG (a recording step): the column's sums of pressure, density and x
+    // momentum of the stored values over the segment's rows, in row order,
+    // with the FP64 closure of the stored values whatever the mode
+    double dsum_p = 0.0, dsum_r = 0.0, dsum_m = 0.0;
     auto store = [&](int k, S q[NC]) {
         if (FINAL) epilogue<S, FAST, NC, EOS>(q, ms, rx, hdt, zlo, zhi, idx, idy, smax, bad);
         const long long o = (long long)k * d.pitch + col;
 #pragma unroll
         for (int c = 0; c < NC; ++c) dst[c * plane + o] = q[c];
+        if constexpr (DIAG) {
+            double qd[NC], wd[NC], rr, rc;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qd[c] = (double)q[c];
+            cons_to_prim<double, 0, NC, EOS>(mix_of<double>(d), qd, wd, rr, rc);
+            dsum_p = dsum_p + wd[4];
+            dsum_r = dsum_r + (qd[0] + qd[1]);
+            dsum_m = dsum_m + qd[2];
+        }
     };
 
     if (MODE == kX) {
@@ -805,6 +819,14 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             }
         }
     }
+    if constexpr (DIAG) {   // this segment's column sums (segments in row order)
+        if (out_col) {
+            double *part = d.diag + (long long)by * 3 * d.nx;
+            part[col] = dsum_p;
+            part[d.nx + col] = dsum_r;
+            part[2 * d.nx + col] = dsum_m;
+        }
+    }
     if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
 }
 
@@ -821,6 +843,18 @@ __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void step_kernel(Desc d, i
     __shared__ R sH[NC][kThreads];
     if (d.ctl->skip) return;
     run_tile<S, R, FAST, LIM, MODE, FINAL, NC, EOS>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
+}
+
+// The fused step of a recording step (transverse averages summed in the store
+// epilogue), held to at least two waves per SIMD like the plain FP64 kernel.
+template <class S, class R, int FAST, int LIM, int MODE, int NC, int EOS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void
+record_step_kernel(Desc d, int src_idx) {
+    __shared__ R sWF[NC + 1][kThreads];
+    __shared__ R sH[NC][kThreads];
+    if (d.ctl->skip) return;
+    run_tile<S, R, FAST, LIM, MODE, true, NC, EOS, false, true>(d, blockIdx.x, blockIdx.y,
+                                                                 src_idx, sWF, sH);
 }
 
 // Fused state update of many solves in one launch: workgroup b takes tile
@@ -871,9 +905,16 @@ template <class S, class R, int FAST, int LIM, int NC, int EOS>
 void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
     void (*k)(Desc, int);
+    const bool diag = d.diag != nullptr;   // a recording step (fused sweeps only)
     switch (mode) {
-        case kXY: k = step_kernel<S, R, FAST, LIM, kXY, true, NC, EOS>; break;
-        case kYX: k = step_kernel<S, R, FAST, LIM, kYX, true, NC, EOS>; break;
+        case kXY:
+            k = diag ? record_step_kernel<S, R, FAST, LIM, kXY, NC, EOS>
+                     : step_kernel<S, R, FAST, LIM, kXY, true, NC, EOS>;
+            break;
+        case kYX:
+            k = diag ? record_step_kernel<S, R, FAST, LIM, kYX, NC, EOS>
+                     : step_kernel<S, R, FAST, LIM, kYX, true, NC, EOS>;
+            break;
         case kX:
             k = final_pass ? step_kernel<S, R, FAST, LIM, kX, true, NC, EOS>
                            : step_kernel<S, R, FAST, LIM, kX, false, NC, EOS>;

@@ -66,6 +66,9 @@ struct Desc {
     // reactive liquid: Gamma0 and c_v (temperature, Eq. (5)); Arrhenius C, Ta
     // and heat of reaction Q (Eq. (6), Table 3)
     double cG0, rxcv, rxC, rxTa, rxQ;
+    // a recording step (fused averages): per segment s, 3 * nx column sums of
+    // pressure, density and x momentum at diag + 3 * nx * s; nullptr otherwise
+    double *diag;
 };
 
 // Host helpers shared by the solver and the server (meso_api.hip).
@@ -116,6 +119,10 @@ hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStre
 hipError_t launch_integrals(const Desc &d, const double *cols, double *out, hipStream_t st);
 hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const double *edges,
                             int nbins, double m_ref, double dn, double *bins, hipStream_t st);
+// One row (p_bar, rho_bar, u_bar; 3 * nx doubles) of a fused-averages record
+// from the segment sums a recording step left at d.diag; NaN if the step was
+// skipped.
+hipError_t launch_diag_row(const Desc &d, double *row, hipStream_t st);
 // Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
 // into descs, strip, segment, unused); every tile of one launch belongs to a
 // solve whose liquid is `eos` and which has `nc` conserved planes (7: reactive).

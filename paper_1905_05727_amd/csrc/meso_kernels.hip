@@ -364,6 +364,29 @@ __global__ void integrals_kernel(int nx, int nc, double area, const double *cols
     out[c] = tot * area;
 }
 
+// One row of a fused-averages record: thread i adds column i's segment sums
+// of a recording step in segment (row) order and forms p_bar = sum p / ny,
+// rho_bar = sum rho / ny, u_bar = sum rho u / sum rho; a skipped step gives NaN.
+__global__ void diag_row_kernel(const Control *ctl, const double *part, int nsegs, int nx,
+                                int ny, double *row) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx) return;
+    if (ctl->skip) {
+        row[i] = row[nx + i] = row[2 * nx + i] = __longlong_as_double(0x7FF8000000000000LL);
+        return;
+    }
+    double sp = 0.0, sr = 0.0, sm = 0.0;
+    for (int g = 0; g < nsegs; ++g) {
+        const double *b = part + (long long)g * 3 * nx;
+        sp = sp + b[i];
+        sr = sr + b[nx + i];
+        sm = sm + b[2 * nx + i];
+    }
+    row[i] = sp / (double)ny;
+    row[nx + i] = sr / (double)ny;
+    row[2 * nx + i] = sm / sr;
+}
+
 constexpr int kMaxBins = 1024;
 
 // Mass-weighted histogram over log-spaced bins: bin a (edges[a] <= v <
@@ -535,6 +558,12 @@ hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStre
     if (prec == kP32) k = d.nc == 7 ? column_kernel<float, 7> : column_kernel<float, 6>;
     else k = d.nc == 7 ? column_kernel<double, 7> : column_kernel<double, 6>;
     hipLaunchKernelGGL(k, dim3(g), dim3(kColThreads), 0, st, d, src, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_row(const Desc &d, double *row, hipStream_t st) {
+    hipLaunchKernelGGL(diag_row_kernel, dim3((d.nx + 255) / 256), dim3(256), 0, st, d.ctl, d.diag,
+                       d.nsegs, d.nx, d.ny, row);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conser
            "mf_server_request_bytes", "mf_server_create", "mf_server_submit", "mf_server_tick",
            "mf_server_poll", "mf_server_finished", "mf_server_result", "mf_server_drain",
            "mf_server_get_stats",
-           "mf_server_destroy", "mf_stream_copy", "mf_integrals_noalloc"]
+           "mf_server_destroy", "mf_stream_copy", "mf_integrals_noalloc",
+           "mf_record_averages", "mf_recorded_rows"]
 
 
 class MesoError(RuntimeError):
@@ -139,6 +140,8 @@ def load_library():
         "mf_y_averages": (C.c_int32, [P, D, D, D, C.c_size_t]),
         "mf_integrals": (C.c_int32, [P, D, C.c_size_t]),
         "mf_integrals_noalloc": (C.c_int32, [P, D, C.c_size_t]),
+        "mf_record_averages": (C.c_int32, [P, P, C.c_int64]),
+        "mf_recorded_rows": (C.c_int32, [P, I64]),
         "mf_log_histogram": (C.c_int32, [P, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                          C.c_double, D]),
         "mf_destroy": (C.c_int32, [P]),
@@ -313,6 +316,18 @@ class Solver:
         return out
 
     # -------------------------------------------------------------- timing
+    def record_averages(self, rows_ptr: int, max_rows: int) -> None:
+        """Record fused transverse averages into device memory at `rows_ptr`
+        (e.g. ``torch.empty(max_rows, 3, nx, dtype=float64, device="cuda")
+        .data_ptr()``); 0 stops recording."""
+        _chk("mf_record_averages", self._lib.mf_record_averages(
+            self._h, C.c_void_p(rows_ptr or None), int(max_rows)))
+
+    def recorded_rows(self) -> int:
+        n = C.c_int64()
+        _chk("mf_recorded_rows", self._lib.mf_recorded_rows(self._h, C.byref(n)))
+        return n.value
+
     def enable_timing(self, on: bool = True) -> None:
         _chk("mf_enable_timing", self._lib.mf_enable_timing(self._h, 1 if on else 0))
 

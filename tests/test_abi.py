@@ -129,6 +129,8 @@ def test_null_handles_are_rejected():
     assert lib.mf_read_field(None, 0, None, 0) == -1
     assert lib.mf_get_time(None, None, None, None) == -1
     assert lib.mf_integrals_noalloc(None, None, 6) == -1
+    assert lib.mf_record_averages(None, None, 1) == -1
+    assert lib.mf_recorded_rows(None, None) == -1
     assert lib.mf_create(None, None, None, None, 0, None, None) == -1
     n = C.c_int32()
     assert lib.mf_server_finished(None, None, 0, C.byref(n)) == -1

@@ -755,3 +755,92 @@ def test_diagnostics_match_oracle_full_width(prec):
         assert np.count_nonzero(fo) > 5, name
         assert np.array_equal(f > 0, nz), name
         np.testing.assert_allclose(f, fo, rtol=rtol, atol=0, err_msg=name)
+
+
+# --------------------------------------------------- fused averages (x-t) ----
+U_ROUND = 2.0 ** -53
+
+
+def check_row(row, ref, U, what):
+    """row, ref: (3, nx) p_bar, rho_bar, u_bar from two summation orders of
+    the same state U (conserved planes)."""
+    ny = U.shape[1]
+    k = 2.0 * ny * U_ROUND
+    pb, rb, ub = row
+    po, ro, uo = ref
+    srho = (U[0] + U[1]).sum(axis=0)
+    smu = np.abs(U[2]).sum(axis=0)
+    # pressure and density are positive: sum of magnitudes = the sum itself
+    assert np.all(np.abs(pb - po) <= k * po * 1.0000001 + 1e-300), what
+    assert np.all(np.abs(rb - ro) <= k * ro * 1.0000001), what
+    tol_u = (k * smu + np.abs(uo) * k * srho) / srho + 2 * U_ROUND * np.abs(uo)
+    assert np.all(np.abs(ub - uo) <= tol_u * 1.0000001 + 1e-300), what
+    d = np.abs(np.stack([pb, rb, ub]) - np.stack([po, ro, uo]))
+    say(f"{what}: largest differences p {d[0].max():.2e} rho {d[1].max():.2e} "
+        f"u {d[2].max():.2e}, exactly equal {float(np.mean(d == 0)):.3f}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64_fast", "fp32_fp64acc", "fp32"])
+def test_recorded_averages_match_unfused_and_oracle(prec):
+    """Fused transverse averages (Sec. 4.2) of 12 recorded steps of a bubble
+    (300 x 140, several segments per strip): recording leaves the state bit
+    for bit unchanged; every row equals mf_y_averages of the state after that
+    step, and the last row the oracle's averages, within the bound of two
+    summation orders (2 ny u of the sum of magnitudes)."""
+    sc = bubble(300, 140)
+    nsteps = 12
+    say(f"case: recorded averages 300x140, {prec}")
+    rows = torch.full((nsteps + 2, 3, sc.nx), -1.0, dtype=torch.float64, device="cuda")
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.record_averages(rows.data_ptr(), nsteps)
+        s.run_steps(nsteps + 2)            # the last two steps are past max_rows
+        s.sync()
+        assert s.recorded_rows() == nsteps
+        U_rec = s.read_conserved()
+    rec = rows.cpu().numpy()
+    assert np.all(rec[nsteps:] == -1.0)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        for r in range(nsteps + 2):
+            s.run_steps(1)
+            if r < nsteps:
+                check_row(rec[r], np.stack(s.y_averages()), s.read_conserved(),
+                          f"{prec} row {r} vs mf_y_averages")
+        U = s.read_conserved()
+    assert_bitwise(U_rec, U, "state with and without recording")
+    o = oracle_of(sc)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(nsteps)
+        Un = s.read_conserved()
+    o.U[...] = Un
+    check_row(rec[nsteps - 1], np.stack(o.y_averages()), Un, f"{prec} last row vs oracle")
+
+
+def test_recorded_averages_full_width_and_skipped_steps():
+    """An 8192 x 256 crop of the roofline field in its launch configuration,
+    60 recorded steps in fast FP64: the last row against the oracle's
+    averages of the state; then run-to-time past its end, where the steps the
+    device skips record NaN rows."""
+    sc = roofline_crop()
+    say("case: recorded averages 8192x256, fp64_fast, then run-to-time")
+    rows = torch.zeros((80, 3, sc.nx), dtype=torch.float64, device="cuda")
+    with meso.Solver.from_scenario(sc, precision="fp64_fast") as s:
+        s.record_averages(rows.data_ptr(), 60)
+        s.run_steps(60)
+        U = s.read_conserved()
+        t60, _, _ = s.time()
+        rec = rows.cpu().numpy()
+        o = oracle_of(sc)
+        o.U[...] = U
+        check_row(rec[59], np.stack(o.y_averages()), U, "8192x256 row 59 vs oracle")
+        rows.zero_()
+        s.record_averages(rows.data_ptr(), 80)
+        taken = s.run_to_time(t60 + 5.5e-9)
+        n = s.recorded_rows()
+        assert 1 <= taken < n <= 80, (taken, n)
+        rec = rows.cpu().numpy()
+        assert np.all(np.isfinite(rec[:taken])) and np.all(np.isnan(rec[taken:n]))
+        assert np.all(rec[n:] == 0.0)
+        s.record_averages(0, 0)            # stop
+        s.run_steps(1)
+        s.sync()
+        assert s.recorded_rows() == n
