@@ -58,10 +58,11 @@ namespace meso {
 // Ar<double, 1>: hardware reciprocal refined by one Newton step and the
 // hardware square root (the FP64 closure of the FP32-bulk mode).
 // Ar<double, 2>: the fast FP64 mode -- reciprocal and reciprocal square root
-// from the hardware seeds (about 23 correct bits) refined by two Newton steps,
-// quotients finished with one residual correction, so every result is within
-// a few ulp of the correctly rounded one at about half the instructions of
-// the IEEE sequences.  Ar<float, *>: hardware reciprocal and square root.
+// from the hardware seeds (about 23 correct bits) refined by the second-order
+// series of 1/(1 - e) and (1 - e)^(-1/2) in the seed's residual e (error of
+// order e^3, below the rounding), so every result is within about one ulp of
+// the correctly rounded one at under half the instructions of the IEEE
+// sequences.  Ar<float, *>: hardware reciprocal and square root.
 template <class T, int FAST> struct Ar;
 template <> struct Ar<double, 0> {
     // v^-C and v^-D of the Cochran-Chan reference curves
@@ -102,26 +103,20 @@ template <> struct Ar<double, 2> {
         vc = exp(-C * l);
         vd = exp(-D * l);
     }
-    // 1/a: seed r0 (relative error e0), r1 = r0 + r0 (1 - a r0) (error e0^2),
-    // r2 likewise (below one ulp)
+    // 1/a from the seed r (relative error |e| < 2^-22, e = 1 - a r):
+    // 1/a = r / (1 - e) = r (1 + e + e^2) + O(e^3)
     static __device__ __forceinline__ double rcp(double a) {
-        double r = __builtin_amdgcn_rcp(a);
-        r = __builtin_fma(r, __builtin_fma(-a, r, 1.0), r);
-        return __builtin_fma(r, __builtin_fma(-a, r, 1.0), r);
+        const double r = __builtin_amdgcn_rcp(a);
+        const double e = __builtin_fma(-a, r, 1.0);
+        return __builtin_fma(r, __builtin_fma(e, e, e), r);
     }
-    // a/b: one Newton step on the seed, then the quotient q = a r1 corrected by
-    // its residual a - b q
-    static __device__ __forceinline__ double div(double a, double b) {
-        double r = __builtin_amdgcn_rcp(b);
-        r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
-        const double q = a * r;
-        return __builtin_fma(__builtin_fma(-b, q, a), r, q);
-    }
-    // 1/sqrt(a): y <- y + (y/2)(1 - a y^2), twice
+    static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
+    // 1/sqrt(a) from the seed y (e = 1 - a y^2):
+    // 1/sqrt(a) = y (1 - e)^(-1/2) = y (1 + e/2 + 3 e^2/8) + O(e^3)
     static __device__ __forceinline__ double rsq(double a) {
-        double y = __builtin_amdgcn_rsq(a);
-        y = __builtin_fma(0.5 * y, __builtin_fma(-a * y, y, 1.0), y);
-        return __builtin_fma(0.5 * y, __builtin_fma(-a * y, y, 1.0), y);
+        const double y = __builtin_amdgcn_rsq(a);
+        const double e = __builtin_fma(-(a * y), y, 1.0);
+        return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
     }
     // sqrt(a) = a / sqrt(a), corrected by the residual a - s^2.  For a > 0
     // and finite only (0 gives NaN): the callers flag a non-positive a anyway
