@@ -224,7 +224,9 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
     (solves back to back, one at a time, per-solve launches), then Poisson
     arrivals at 0.8x and 2x that capacity through the batched server and
     through the sequential baseline, and a burst of all requests at once (on a
-    fresh server, then on the warm one)."""
+    fresh server, then on the warm one).  At 2x and in the warm burst, a
+    second sequential baseline: a one-slot server (one solve at a time with
+    its own launches, but no allocation per request)."""
     from paper_1905_05727_amd import scenario, serve
     t = time.perf_counter()
     reqs = scenario.serving_workload(nreq, steps=nsteps)
@@ -243,6 +245,11 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
            "sequential_capacity_req_per_s": cap,
            "sequential_back_to_back_cell_updates_per_s": work / t_seq, "rates": {}}
     budget = 16 << 30
+    # A second sequential baseline without per-request allocation: the same
+    # server machinery with one slot (one solve at a time, its own launches,
+    # pooled pinned buffers), warmed up on a few requests first.
+    one = serve.Server(budget, max_slots=1, precision=precision, max_inflight=8)
+    serve.serve(one, reqs[:8], np.zeros(8), nsteps)
     # One server for every run, as a serving process keeps it: the first burst
     # finds its pinned host pools empty and allocates them (reported as the
     # cold start); the later runs reuse them.
@@ -269,8 +276,17 @@ def serving_bench(nreq: int, nsteps: int, precision: str = "fp32_fp64acc"):
                                        "makespan_s": sq["makespan_s"]}
                 msg += (f" | sequential p50 {1e3 * sq['p50_s']:.1f} ms p99 "
                         f"{1e3 * sq['p99_s']:.1f} ms {sq['cell_updates_per_s'] / 1e9:.2f} G/s")
+                if key in ("2.0x", "burst"):
+                    o1 = serve.serve(one, reqs, arr, nsteps)
+                    entry["sequential_one_slot_server"] = {
+                        "p50_ms": 1e3 * o1["p50_s"], "p99_ms": 1e3 * o1["p99_s"],
+                        "cell_updates_per_s": o1["cell_updates_per_s"],
+                        "makespan_s": o1["makespan_s"]}
+                    msg += (f" | one-slot server p50 {1e3 * o1['p50_s']:.1f} ms p99 "
+                            f"{1e3 * o1['p99_s']:.1f} ms {o1['cell_updates_per_s'] / 1e9:.2f} G/s")
             out["rates"][key] = entry
             log(msg)
+    one.close()
     return out
 
 
