@@ -360,9 +360,9 @@ __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out
 
 // HLLC flux with Davis bounds; out = (5 flux components, u_f, z_f) and, with
 // NC = 7, the reactant-mass flux.  The star state is evaluated once, for the
-// side the contact moves away from; faces with S* == 0 exactly (or NaN)
-// evaluate both sides and average instead.
-template <class R, int FAST, int NC, int EOS>
+// side the contact moves away from; in the FP64 mode faces with S* == 0
+// exactly (or NaN) evaluate both sides and average instead.
+template <class R, int FAST, int NC, int EOS, bool TAVG = FAST == 0>
 __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR[NC],
                                      R out[NC + 1]) {
     Side<R, NC> L, Rs;
@@ -381,9 +381,15 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     // values per lane (same values; in the other kernels that second path
     // would cost occupancy)
     constexpr bool kUniform = sizeof(R) == 8 && FAST != 1 && EOS == 0;
+    // Ties (S* == 0): the two star branches agree there in exact arithmetic
+    // (F*_R - F*_L = S* (U*_R - U*_L)).  With TAVG they are averaged (the FP64
+    // mode's contract, which keeps mirror-symmetric data symmetric to the last
+    // bit; also the FP32-bulk kernel, measured faster so), otherwise the left
+    // branch is taken (fast FP64, FP32: one star evaluation per face)
+    constexpr bool kTieAverage = TAVG;
     R st[NC + 1];
-    if (Ss > R(0) || Ss < R(0)) {
-        const bool useL = Ss > R(0);
+    if (!kTieAverage || Ss > R(0) || Ss < R(0)) {
+        const bool useL = kTieAverage ? Ss > R(0) : !(Ss < R(0));
         auto select_side = [&]() {
             Side<R, NC> K;
             K.rho = useL ? L.rho : Rs.rho;
@@ -429,6 +435,14 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
     out[5] = supL ? L.un : (supR ? Rs.un : st[5]);
     out[6] = supL ? L.z : (supR ? Rs.z : st[6]);
     if constexpr (NC == 7) out[7] = supL ? L.F[5] : (supR ? Rs.F[5] : st[7]);
+}
+
+// Tie rule of the HLLC flux for a kernel with storage type S, flux type R and
+// arithmetic level FAST: average the two star branches at S* == 0 in the FP64
+// mode and in FP32-bulk, take the left one in fast FP64 and FP32.
+template <class S, class R, int FAST>
+constexpr bool tie_average() {
+    return FAST == 0 || sizeof(S) != sizeof(R);
 }
 
 // Update of one cell from its low- and high-face fluxes; fluxes are widened to
@@ -478,7 +492,7 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
         R whm[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) whm[c] = sH[c][t - 1];
-        hllc<R, FAST, NC, EOS>(mr, whm, wl, f);
+        hllc<R, FAST, NC, EOS, tie_average<S, R, FAST>()>(mr, whm, wl, f);
 #pragma unroll
         for (int c = 0; c < NC + 1; ++c) sWF[c][t] = f[c];
     }
@@ -531,7 +545,7 @@ __device__ __forceinline__ void x_row_skip(const S q[NC], S qo[NC], int t, S lam
         R whm[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) whm[c] = sH[c][t - 1];
-        hllc<R, FAST, NC, EOS>(mr, whm, wl, f);
+        hllc<R, FAST, NC, EOS, tie_average<S, R, FAST>()>(mr, whm, wl, f);
 #pragma unroll
         for (int c = 0; c < NC + 1; ++c) sWF[c][t] = f[c];
     }
@@ -573,7 +587,7 @@ struct YPipe {
             face_states<R, FAST, LIM, NC>(w2, w1, wk, r1, c1, hl, wl, wh);
             if (cnt >= 3) {
                 R f[NC + 1];
-                hllc<R, FAST, NC, EOS>(mr, wh2, wl, f);
+                hllc<R, FAST, NC, EOS, tie_average<S, R, FAST>()>(mr, wh2, wl, f);
                 if (cnt >= 4) {
                     update_cell<S, R, NC>(q2, f2, f, lam, qo);
                     out = true;
