@@ -144,20 +144,29 @@ def run_mode(sc, prec, steps, warmup, diagnostics=False, active=None):
 
 
 def time_recording(sc, prec, steps, warmup):
-    """Cost of the fused transverse averages (Sec. 4.2, an x-t row per step):
-    the same steps of the workload timed without and with recording -- state
-    kernel time by HIP events and wall time per step, which with recording
-    includes the small kernel that adds the segment sums into the row."""
+    """Cost of the fused diagnostics: the same steps of the workload timed
+    without recording, recording the transverse averages (Sec. 4.2, an x-t row
+    per step), and recording the averages, the domain integrals (Eq. (10)) and
+    a 400-bin mass-weighted pressure PDF (Sec. 4.5) together -- state kernel
+    time by HIP events and wall time per step, which with recording includes
+    the small kernels that finish each row."""
     import torch
     from paper_1905_05727_amd import meso
     out = {}
+    nbins = 400
     with meso.Solver.from_scenario(sc, precision=prec) as s:
+        m_ref = float(s.integrals()[1])
         s.run_steps(warmup)
         s.sync()
-        rows = torch.empty((steps, 3, sc.nx), dtype=torch.float64, device="cuda")
-        for key, rec in (("plain", False), ("recording", True)):
-            if rec:
-                s.record_averages(rows.data_ptr(), steps)
+        avg = torch.empty((steps, 3, sc.nx), dtype=torch.float64, device="cuda")
+        itg = torch.empty((steps, s.nplanes), dtype=torch.float64, device="cuda")
+        pdf = torch.empty((steps, nbins), dtype=torch.float64, device="cuda")
+        for key in ("plain", "recording", "recording_all"):
+            if key != "plain":
+                s.record_averages(avg.data_ptr(), steps)
+            if key == "recording_all":
+                s.record_integrals(itg.data_ptr(), steps)
+                s.record_histogram("p", 4.0, 0.015, nbins, m_ref, pdf.data_ptr(), steps)
             s.enable_timing(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -168,10 +177,13 @@ def time_recording(sc, prec, steps, warmup):
             out[key] = {"step_kernel_ms": kms / max(launches, 1),
                         "wall_ms_per_step": 1e3 * (t1 - t0) / steps}
             s.record_averages(0, 0)
-        assert bool(torch.isfinite(rows).all())
-        del rows
-    out["extra_ms_per_step"] = (out["recording"]["wall_ms_per_step"]
-                                - out["plain"]["wall_ms_per_step"])
+            s.record_integrals(0, 0)
+            s.record_histogram("p", 4.0, 0.015, nbins, m_ref, 0, 0)
+        assert bool(torch.isfinite(avg).all()) and bool(torch.isfinite(itg).all())
+        assert bool(torch.isfinite(pdf).all()) and float(pdf.sum()) > 0.0
+        del avg, itg, pdf
+    for key, k in (("extra_ms_per_step", "recording"), ("extra_ms_per_step_all", "recording_all")):
+        out[key] = out[k]["wall_ms_per_step"] - out["plain"]["wall_ms_per_step"]
     torch.cuda.empty_cache()
     return out
 
@@ -552,7 +564,10 @@ def main():
         for m, f in fused.items():
             log(f"fused averages {m}: step kernel {f['plain']['step_kernel_ms']:.3f} -> "
                 f"{f['recording']['step_kernel_ms']:.3f} ms, wall +{f['extra_ms_per_step']:.3f} "
-                f"ms per step (separate pass {g['y_averages']:.3f} ms)")
+                f"ms per step (separate pass {g['y_averages']:.3f} ms); with integrals and "
+                f"pressure PDF {f['recording_all']['step_kernel_ms']:.3f} ms, wall "
+                f"+{f['extra_ms_per_step_all']:.3f} ms (separate passes "
+                f"{g['y_averages'] + g['integrals'] + g['pdf_p']:.3f} ms)")
         line["diagnostics"] = {
             "fused_averages": fused,
             "state": "FP64 roofline field after the timed steps", "bytes_read": nbytes,

@@ -278,6 +278,50 @@ int32_t mf_record_averages(mf_solver *s, double *dev_rows, int64_t max_rows);
  * them, e.g. after mf_sync).  Does not synchronise. */
 int32_t mf_recorded_rows(mf_solver *s, int64_t *rows);
 
+/* Fused domain integrals, for the remaining reactant mass M_2,r(t) of Eq.
+ * (10) and the global rate of Eq. (11) at every step: while recording, each
+ * step also sums every conserved plane of the state it stores, in its store
+ * epilogue, and writes one row of nc doubles (the values of mf_integrals:
+ * z1 rho1, z2 rho2, rho u, rho v, rho E, z1 and, reactive, M_2,r; nc = 6 or
+ * 7) to dev_rows: row r is the state after the r-th step enqueued since this
+ * call, NaN for a step the device skipped.  Each workgroup sums its cells
+ * (a column's rows in order, then a fixed tree over its columns) and the
+ * workgroup sums are added in launch order, so a value may differ from
+ * mf_integrals of the same state by up to 2 N u of the sum of magnitudes
+ * (N cells, u = 2^-53) and depends on nothing but the grid and the launch
+ * geometry.  dev_rows: device memory of at least nc*max_rows doubles, owned
+ * by the caller and kept alive while recording; NULL stops.  Fused solvers
+ * only; the first call allocates nc doubles per workgroup of the step launch
+ * (freed by mf_destroy).  MF_E_INVALID_ARG (unfused solver, max_rows < 1,
+ * misaligned pointer), MF_E_OUT_OF_MEMORY.  Enqueues nothing itself. */
+int32_t mf_record_integrals(mf_solver *s, double *dev_rows, int64_t max_rows);
+
+/* Fused mass-weighted PDF (Sec. 4.5) at every step: while recording, each
+ * step also adds the liquid mass z2 rho2 dx dy of every cell it stores to the
+ * log-spaced bin of its field value, in its store epilogue, with the bins,
+ * field and arguments of mf_log_histogram (MF_P, MF_RHO or, reactive,
+ * MF_QDOT; bin edges 10^(lo + k dn); f = m_k / (m_ref dn)), and writes one row
+ * of nbins doubles to dev_rows: row r after the r-th step enqueued since this
+ * call, NaN for a step the device skipped.  The bins collect in the
+ * workgroup's local memory, then one atomic addition per workgroup and
+ * non-empty bin: a bin may differ from mf_log_histogram of the same state by
+ * the order of its additions (up to 2 N u of the bin's mass); a cell whose
+ * value lies within rounding of a bin edge may fall in the neighbouring bin
+ * (the recording kernels of the fast modes fuse multiply-adds in the FP64
+ * closure).  dev_rows: device memory of at least nbins*max_rows doubles,
+ * owned by the caller; NULL stops.  Fused solvers only.  The bin edges are
+ * copied to library-owned device memory (1025 doubles, allocated on first
+ * use): synchronises the solver's stream.  MF_E_INVALID_ARG (as for
+ * mf_log_histogram, or an unfused solver, max_rows < 1, misaligned pointer),
+ * MF_E_OUT_OF_MEMORY, MF_E_DEVICE. */
+int32_t mf_record_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
+                            double m_ref, double *dev_rows, int64_t max_rows);
+
+/* Rows enqueued by the three fused records since each was started: counts[0]
+ * averages, counts[1] integrals, counts[2] histogram.  Does not
+ * synchronise. */
+int32_t mf_recorded_counts(mf_solver *s, int64_t counts[3]);
+
 /* Kernel timing: when enabled, every step kernel launch is bracketed by HIP
  * events on the solver's stream.  mf_kernel_time synchronises and returns the
  * summed duration (ms) and launch count of the state-update kernels since

@@ -158,7 +158,10 @@ void set_segments(Desc &d, int ny, int h, int h2, int tail_rows) {
 void fill_desc(Desc &d, const mf_grid *g, const mf_material *mat, const mf_options *opt,
                char *base, int seg_h) {
     d.ctl = (Control *)base;
-    d.diag = nullptr;
+    d.diag = d.dint = d.dhist = nullptr;
+    d.hedges = nullptr;
+    d.hbins = d.hfield = 0;
+    d.hlo = d.hidn = 0.0f;
     d.buf[0] = base + kAlign;
     d.nc = planes_of(mat);
     d.buf[1] = base + kAlign + state_bytes(g, opt->precision, d.nc);
@@ -241,6 +244,14 @@ struct EventPair {
     hipEvent_t a, b;
 };
 
+// One fused record: the caller's device rows, their number and the rows
+// enqueued so far.
+struct Record {
+    double *rows;
+    int64_t max, done;
+    bool active() const { return rows && done < max; }
+};
+
 }  // namespace
 
 struct mf_solver {
@@ -257,11 +268,15 @@ struct mf_solver {
     std::vector<EventPair> ev;
     size_t ev_used;
     int device;           // HIP device current at creation
-    // fused averages: segment sums (library-owned), the caller's rows, their
-    // number and the rows enqueued so far
-    double *rec_part;
-    double *rec_rows;
-    int64_t rec_max, rec_done;
+    // fused recording: library-owned partial sums and bin edges (allocated
+    // on first use, freed by mf_destroy) and the caller's records
+    double *rec_part;     // averages: 3 * nx column sums per segment
+    double *int_part;     // integrals: nc sums per workgroup
+    double *hist_edges;   // histogram: nbins + 1 edges (up to 1025)
+    Record rec_avg, rec_int, rec_hist;
+    int hist_bins, hist_field;
+    double hist_mdn;      // m_ref * dn of the recorded histogram
+    float hist_lo, hist_idn;   // lo and 1 / dn (the bin guess)
 };
 
 // Scratch of mf_integrals_noalloc: the column sums ((3 + nc) * nx doubles)
@@ -349,6 +364,12 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
     if (e != hipSuccess) return MF_E_DEVICE;
     const long long n = s->host_step;
     const int prec = s->opt.precision, lim = s->opt.limiter;
+    const bool ra = s->opt.fused && s->rec_avg.active();
+    const bool ri = s->opt.fused && s->rec_int.active();
+    const bool rh = s->opt.fused && s->rec_hist.active();
+    double *hrow = rh ? s->rec_hist.rows + s->rec_hist.done * (int64_t)s->hist_bins : nullptr;
+    if (rh && meso::launch_hist_clear(hrow, s->hist_bins, s->stream) != hipSuccess)
+        return MF_E_DEVICE;
     EventPair *ep = nullptr;
     if (s->timing) {
         if (s->ev_used == s->ev.size()) {
@@ -360,10 +381,16 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
         ep = &s->ev[s->ev_used++];
         if (hipEventRecord(ep->a, s->stream) != hipSuccess) return MF_E_DEVICE;
     }
-    const bool rec = s->opt.fused && s->rec_rows && s->rec_done < s->rec_max;
     if (s->opt.fused) {
         const int src = (int)(n & 1);
-        if (rec) s->d.diag = s->rec_part;
+        s->d.diag = ra ? s->rec_part : nullptr;
+        s->d.dint = ri ? s->int_part : nullptr;
+        s->d.dhist = hrow;
+        s->d.hedges = s->hist_edges;
+        s->d.hbins = s->hist_bins;
+        s->d.hfield = s->hist_field;
+        s->d.hlo = s->hist_lo;
+        s->d.hidn = s->hist_idn;
         e = meso::launch_step(s->d, prec, lim, (n & 1) ? meso::kYX : meso::kXY, 1, src,
                               s->stream);
     } else {
@@ -373,22 +400,36 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
         e = meso::launch_step(s->d, prec, lim, first, 0, 0, s->stream);
         if (e == hipSuccess) e = meso::launch_step(s->d, prec, lim, second, 1, 1, s->stream);
     }
-    if (e != hipSuccess) {
-        s->d.diag = nullptr;
-        return MF_E_DEVICE;
+    if (e == hipSuccess && ep && hipEventRecord(ep->b, s->stream) != hipSuccess)
+        e = hipErrorUnknown;
+    if (e == hipSuccess && ra) {
+        e = meso::launch_diag_row(
+            s->d, s->rec_avg.rows + s->rec_avg.done * 3 * (int64_t)s->grid.nx, s->stream);
+        ++s->rec_avg.done;
     }
-    if (ep && hipEventRecord(ep->b, s->stream) != hipSuccess) {
-        s->d.diag = nullptr;
-        return MF_E_DEVICE;
+    if (e == hipSuccess && ri) {
+        e = meso::launch_int_row(s->d, s->rec_int.rows + s->rec_int.done * (int64_t)s->d.nc,
+                                 s->stream);
+        ++s->rec_int.done;
     }
-    if (rec) {
-        e = meso::launch_diag_row(s->d, s->rec_rows + s->rec_done * 3 * (int64_t)s->grid.nx,
-                                  s->stream);
-        s->d.diag = nullptr;
-        if (e != hipSuccess) return MF_E_DEVICE;
-        ++s->rec_done;
+    if (e == hipSuccess && rh) {
+        e = meso::launch_hist_finish(s->d, hrow, s->hist_bins, s->hist_mdn, s->stream);
+        ++s->rec_hist.done;
     }
+    s->d.diag = s->d.dint = s->d.dhist = nullptr;
+    if (e != hipSuccess) return MF_E_DEVICE;
     s->host_step = n + 1;
+    return MF_OK;
+}
+
+// A library-owned device buffer of n doubles, allocated on first use.
+int32_t alloc_once(double **p, size_t n) {
+    if (*p) return MF_OK;
+    if (hipMalloc(p, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return MF_E_OUT_OF_MEMORY;
+    }
     return MF_OK;
 }
 
@@ -726,28 +767,78 @@ int32_t mf_launch_info(mf_solver *s, int64_t *workgroups, int32_t *threads, int3
 int32_t mf_record_averages(mf_solver *s, double *dev_rows, int64_t max_rows) {
     if (!s) return MF_E_INVALID_ARG;
     if (!dev_rows) {   // stop recording; the rows written stay the caller's
-        s->rec_rows = nullptr;
+        s->rec_avg.rows = nullptr;
         return MF_OK;
     }
     if (!s->opt.fused || max_rows < 1 || ((uintptr_t)dev_rows % sizeof(double)) != 0)
         return MF_E_INVALID_ARG;
-    if (!s->rec_part) {
-        const size_t n = 3 * (size_t)s->grid.nx * s->d.nsegs;
-        if (hipMalloc(&s->rec_part, n * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            s->rec_part = nullptr;
-            return MF_E_OUT_OF_MEMORY;
-        }
+    const int32_t st = alloc_once(&s->rec_part, 3 * (size_t)s->grid.nx * s->d.nsegs);
+    if (st != MF_OK) return st;
+    s->rec_avg = Record{dev_rows, max_rows, 0};
+    return MF_OK;
+}
+
+int32_t mf_record_integrals(mf_solver *s, double *dev_rows, int64_t max_rows) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (!dev_rows) {
+        s->rec_int.rows = nullptr;
+        return MF_OK;
     }
-    s->rec_rows = dev_rows;
-    s->rec_max = max_rows;
-    s->rec_done = 0;
+    if (!s->opt.fused || max_rows < 1 || ((uintptr_t)dev_rows % sizeof(double)) != 0)
+        return MF_E_INVALID_ARG;
+    const int32_t st =
+        alloc_once(&s->int_part, (size_t)s->d.nc * s->d.nstrips * (size_t)s->d.nsegs);
+    if (st != MF_OK) return st;
+    s->rec_int = Record{dev_rows, max_rows, 0};
+    return MF_OK;
+}
+
+int32_t mf_record_histogram(mf_solver *s, int32_t field, double lo, double dn, int32_t nbins,
+                            double m_ref, double *dev_rows, int64_t max_rows) {
+    if (!s) return MF_E_INVALID_ARG;
+    if (!dev_rows) {
+        s->rec_hist.rows = nullptr;
+        return MF_OK;
+    }
+    if (!s->opt.fused || max_rows < 1 || ((uintptr_t)dev_rows % sizeof(double)) != 0 ||
+        (field != MF_P && field != MF_RHO && !(field == MF_QDOT && s->d.nc == 7)) ||
+        nbins < 1 || nbins > 1024 || !(dn > 0.0) || !isfinite(lo) || !isfinite(dn) ||
+        !(m_ref > 0.0))
+        return MF_E_INVALID_ARG;
+    int32_t st = alloc_once(&s->hist_edges, 1025);
+    if (st != MF_OK) return st;
+    // the same edges as mf_log_histogram; the stream may still be reading
+    // the previous ones
+    std::vector<double> edges(nbins + 1);
+    for (int32_t k = 0; k <= nbins; ++k) edges[k] = pow(10.0, lo + (double)k * dn);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->hist_edges, edges.data(), sizeof(double) * (nbins + 1),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        s->rec_hist.rows = nullptr;
+        return dev_err(e);
+    }
+    s->hist_bins = nbins;
+    s->hist_field = field;
+    s->hist_mdn = m_ref * dn;
+    s->hist_lo = (float)lo;
+    s->hist_idn = (float)(1.0 / dn);
+    s->rec_hist = Record{dev_rows, max_rows, 0};
     return MF_OK;
 }
 
 int32_t mf_recorded_rows(mf_solver *s, int64_t *rows) {
     if (!s || !rows) return MF_E_INVALID_ARG;
-    *rows = s->rec_done;
+    *rows = s->rec_avg.done;
+    return MF_OK;
+}
+
+int32_t mf_recorded_counts(mf_solver *s, int64_t counts[3]) {
+    if (!s || !counts) return MF_E_INVALID_ARG;
+    counts[0] = s->rec_avg.done;
+    counts[1] = s->rec_int.done;
+    counts[2] = s->rec_hist.done;
     return MF_OK;
 }
 
@@ -755,6 +846,8 @@ int32_t mf_destroy(mf_solver *s) {
     if (!s) return MF_E_INVALID_ARG;
     hipError_t e = hipStreamSynchronize(s->stream);
     if (s->rec_part) (void)hipFree(s->rec_part);
+    if (s->int_part) (void)hipFree(s->int_part);
+    if (s->hist_edges) (void)hipFree(s->hist_edges);
     for (auto &p : s->ev) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

@@ -697,6 +697,30 @@ __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S
 
 // Pointwise stage and CFL contribution of one updated cell (U order): the z1
 // clamp, the second half of the reaction (NC = 7), then the signal speed.
+// Liquid temperature of Eq. (5) (T_ref = 0, constant Gamma_0 and c_v) of a
+// cell of a reactive Cochran-Chan liquid, evaluated in FP64.
+__device__ __forceinline__ double liquid_temperature(const Mix<double> &m, const Rx<double> &x,
+                                                     const double q[7]) {
+    double w[7], r, rc2;
+    cons_to_prim<double, false, 7>(m, q, w, r, rc2);
+    const double rho2 = q[1] / (1.0 - q[5]);
+    const double v = m.rho0 / rho2;
+    double vc, vd;
+    Ar<double, false>::pw(v, m.C, m.D, vc, vd);
+    const double pref = m.A * vc - m.B * vd;
+    return (w[4] - pref) / ((rho2 * x.G0) * x.cv);
+}
+
+// Volumetric heat-release rate -z2 rho2 K Q of the reactive liquid (Sec. 4.5)
+// in GW/m^3; 0 without reactant or at T2 <= 0.
+__device__ __forceinline__ double heat_release(const Mix<double> &m, const Rx<double> &x,
+                                               const double q[7]) {
+    if (!(q[6] > 0.0)) return 0.0;
+    const double T = liquid_temperature(m, x, q);
+    if (!(T > 0.0)) return 0.0;
+    return ((q[6] * x.C) * exp(-x.Ta / T) * x.Q) * 1.0e-9;
+}
+
 template <class S, int FAST, int NC, int EOS>
 __device__ __forceinline__ void epilogue(S q[NC], const Mix<S> &ms, const Rx<S> &rx, S hdt,
                                          S zlo, S zhi, S idx, S idy, S &smax, int &bad) {
@@ -739,6 +763,33 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
     }
 }
 
+// Workgroup sums of N per-thread values, written to out[0..N-1]: a butterfly
+// within each wave (every lane ends with the same bits, the two operands of
+// each addition being the same pair in either order), then the waves in
+// order, so the result depends only on the values and their lanes.
+template <int N>
+__device__ __forceinline__ void block_sums(const double v[N], double *out) {
+    __shared__ double red[kThreads / 64][N];
+    double s[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        s[c] = v[c];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s[c] = s[c] + __shfl_xor(s[c], off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) red[wv][c] = s[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double a = red[0][threadIdx.x];
+        for (int i = 1; i < kThreads / 64; ++i) a = a + red[i][threadIdx.x];
+        out[threadIdx.x] = a;
+    }
+}
+
 // ------------------------------------------------------------------------
 // One tile of the state update: strip bx (252 written columns) and row
 // segment by of the solve described by d.  MODE: kXY / kYX (fused step), kX /
@@ -748,9 +799,11 @@ __device__ __forceinline__ void block_cfl_commit(double smax, int bad, Control *
 // every value it loads, halo cells included.  All threads of the workgroup
 // call it.
 template <class S, class R, int FAST, int LIM, int MODE, bool FINAL, int NC, int EOS,
-          bool SKIP = false, bool DIAG = false>
+          bool SKIP = false, int DIAG = 0>
 __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_idx,
-                                         R (*sWF)[kThreads], R (*sH)[kThreads]) {
+                                         R (*sWF)[kThreads], R (*sH)[kThreads],
+                                         double *sEdge = nullptr, double *sHist = nullptr,
+                                         double (*sInt)[kThreads] = nullptr) {
     Control *ctl = d.ctl;
     const S lamx = (S)ctl->lam_x, lamy = (S)ctl->lam_y;
     const R hlx = (R)ctl->hl_x, hly = (R)ctl->hl_y;
@@ -800,23 +853,71 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     auto start = [&](S q[NC]) {
         if constexpr (NC == 7 && kStarts) react<S, FAST>(q, ms, rx, hdt);
     };
-    // DIAG (a recording step): the column's sums of pressure, density and x
-    // momentum of the stored values over the segment's rows, in row order,
-    // with the FP64 closure of the stored values whatever the mode
+    // DIAG (a recording step), on the stored values in FP64 (the FP64 closure
+    // whatever the mode): the column's sums of pressure, density and x
+    // momentum over the segment's rows in row order (d.diag); the column's
+    // sums of every stored plane (d.dint; running sums in LDS, sInt, one
+    // slot per thread, to spare registers); the liquid mass of each cell
+    // added to the workgroup's bin of its pressure, density or heat-release
+    // rate (d.dhist; bins in LDS, sHist)
     double dsum_p = 0.0, dsum_r = 0.0, dsum_m = 0.0;
+    // the histogram's pending bin of this thread and its mass: cells down a
+    // column mostly share a bin, so one LDS atomic per run of them
+    [[maybe_unused]] int hbin = -1;
+    [[maybe_unused]] double hmass = 0.0;
+    if constexpr (DIAG) {
+        if (d.dint) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sInt[c][t] = 0.0;
+        }
+    }
     auto store = [&](int k, S q[NC]) {
         if (FINAL) epilogue<S, FAST, NC, EOS>(q, ms, rx, hdt, zlo, zhi, idx, idy, smax, bad);
         const long long o = (long long)k * d.pitch + col;
 #pragma unroll
         for (int c = 0; c < NC; ++c) dst[c * plane + o] = q[c];
         if constexpr (DIAG) {
-            double qd[NC], wd[NC], rr, rc;
+            double qd[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) qd[c] = (double)q[c];
-            cons_to_prim<double, 0, NC, EOS>(mix_of<double>(d), qd, wd, rr, rc);
-            dsum_p = dsum_p + wd[4];
-            dsum_r = dsum_r + (qd[0] + qd[1]);
-            dsum_m = dsum_m + qd[2];
+            if (d.dint) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sInt[c][t] = sInt[c][t] + qd[c];
+            }
+            double v = 0.0;
+            if (d.diag || (DIAG == 2 && d.hfield != MF_QDOT)) {
+                double wd[NC], rr, rc;
+                cons_to_prim<double, 0, NC, EOS>(mix_of<double>(d), qd, wd, rr, rc);
+                if (d.diag) {
+                    dsum_p = dsum_p + wd[4];
+                    dsum_r = dsum_r + (qd[0] + qd[1]);
+                    dsum_m = dsum_m + qd[2];
+                }
+                v = d.hfield == MF_RHO ? qd[0] + qd[1] : wd[4];
+            }
+            if constexpr (DIAG == 2) {
+                if constexpr (NC == 7) {
+                    if (d.hfield == MF_QDOT) v = heat_release(mix_of<double>(d), rx_of<double>(d), qd);
+                }
+                const int nb = d.hbins;
+                if (v >= sEdge[0] && v < sEdge[nb]) {
+                    // the bin a with e[a] <= v < e[a+1]: a guess from the
+                    // FP32 logarithm, then decided by the FP64 edges (the
+                    // same bin as a search over the edges)
+                    const float g = (__log2f((float)v) * 0.30102999566f - d.hlo) * d.hidn;
+                    int a = min(max((int)g, 0), nb - 1);
+                    while (a > 0 && v < sEdge[a]) --a;
+                    while (a < nb - 1 && v >= sEdge[a + 1]) ++a;
+                    const double m = qd[1] * (d.dx * d.dy);
+                    if (a == hbin) {
+                        hmass = hmass + m;
+                    } else {
+                        if (hbin >= 0) atomicAdd(&sHist[hbin], hmass);
+                        hbin = a;
+                        hmass = m;
+                    }
+                }
+            }
         }
     };
 
@@ -884,12 +985,24 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
             }
         }
     }
-    if constexpr (DIAG) {   // this segment's column sums (segments in row order)
-        if (out_col) {
+    if constexpr (DIAG) {
+        if (d.diag && out_col) {   // this segment's column sums (segments in row order)
             double *part = d.diag + (long long)by * 3 * d.nx;
             part[col] = dsum_p;
             part[d.nx + col] = dsum_r;
             part[2 * d.nx + col] = dsum_m;
+        }
+        if (d.dint) {
+            double isum[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) isum[c] = sInt[c][t];
+            block_sums<NC>(isum, d.dint + (long long)NC * ((long long)by * d.nstrips + bx));
+        }
+        if constexpr (DIAG == 2) {   // the workgroup's bins into the step's row
+            if (hbin >= 0) atomicAdd(&sHist[hbin], hmass);
+            __syncthreads();
+            for (int b = t; b < d.hbins; b += kThreads)
+                if (sHist[b] != 0.0) atomicAdd(&d.dhist[b], sHist[b]);
         }
     }
     if (FINAL) block_cfl_commit((double)smax, bad, ctl, slot);
@@ -910,16 +1023,27 @@ __global__ __launch_bounds__(kThreads) MESO_STEP_ATTR void step_kernel(Desc d, i
     run_tile<S, R, FAST, LIM, MODE, FINAL, NC, EOS>(d, blockIdx.x, blockIdx.y, src_idx, sWF, sH);
 }
 
-// The fused step of a recording step (transverse averages summed in the store
+// The fused step of a recording step (diagnostics summed in the store
 // epilogue), held to at least two waves per SIMD like the plain FP64 kernel.
-template <class S, class R, int FAST, int LIM, int MODE, int NC, int EOS>
+// HIST: a histogram is recorded (a variant of its own, so that the other
+// recordings keep the registers it needs); dynamic LDS holds its edges and
+// bins (2 hbins + 1 doubles).
+template <class S, class R, int FAST, int LIM, int MODE, int NC, int EOS, bool HIST>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void
 record_step_kernel(Desc d, int src_idx) {
     __shared__ R sWF[NC + 1][kThreads];
     __shared__ R sH[NC][kThreads];
+    __shared__ double sInt[NC][kThreads];
+    extern __shared__ double sHistMem[];
     if (d.ctl->skip) return;
-    run_tile<S, R, FAST, LIM, MODE, true, NC, EOS, false, true>(d, blockIdx.x, blockIdx.y,
-                                                                 src_idx, sWF, sH);
+    double *sEdge = sHistMem, *sHist = sHistMem + d.hbins + 1;
+    if constexpr (HIST) {
+        for (int b = threadIdx.x; b <= d.hbins; b += kThreads) sEdge[b] = d.hedges[b];
+        for (int b = threadIdx.x; b < d.hbins; b += kThreads) sHist[b] = 0.0;
+        __syncthreads();
+    }
+    run_tile<S, R, FAST, LIM, MODE, true, NC, EOS, false, HIST ? 2 : 1>(
+        d, blockIdx.x, blockIdx.y, src_idx, sWF, sH, sEdge, sHist, sInt);
 }
 
 // Fused state update of many solves in one launch: workgroup b takes tile
@@ -970,15 +1094,19 @@ template <class S, class R, int FAST, int LIM, int NC, int EOS>
 void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, hipStream_t st) {
     const dim3 grid(d.nstrips, d.nsegs), block(kThreads);
     void (*k)(Desc, int);
-    const bool diag = d.diag != nullptr;   // a recording step (fused sweeps only)
+    // a recording step (fused sweeps only)
+    const bool diag = d.diag != nullptr || d.dint != nullptr || d.dhist != nullptr;
+    const size_t lds = (diag && d.dhist) ? sizeof(double) * (2 * (size_t)d.hbins + 1) : 0;
     switch (mode) {
         case kXY:
-            k = diag ? record_step_kernel<S, R, FAST, LIM, kXY, NC, EOS>
-                     : step_kernel<S, R, FAST, LIM, kXY, true, NC, EOS>;
+            k = !diag    ? step_kernel<S, R, FAST, LIM, kXY, true, NC, EOS>
+                : d.dhist ? record_step_kernel<S, R, FAST, LIM, kXY, NC, EOS, true>
+                          : record_step_kernel<S, R, FAST, LIM, kXY, NC, EOS, false>;
             break;
         case kYX:
-            k = diag ? record_step_kernel<S, R, FAST, LIM, kYX, NC, EOS>
-                     : step_kernel<S, R, FAST, LIM, kYX, true, NC, EOS>;
+            k = !diag    ? step_kernel<S, R, FAST, LIM, kYX, true, NC, EOS>
+                : d.dhist ? record_step_kernel<S, R, FAST, LIM, kYX, NC, EOS, true>
+                          : record_step_kernel<S, R, FAST, LIM, kYX, NC, EOS, false>;
             break;
         case kX:
             k = final_pass ? step_kernel<S, R, FAST, LIM, kX, true, NC, EOS>
@@ -989,7 +1117,7 @@ void launch_step_variants_eos(const Desc &d, int mode, int final_pass, int src, 
                            : step_kernel<S, R, FAST, LIM, kY, false, NC, EOS>;
             break;
     }
-    hipLaunchKernelGGL(k, grid, block, 0, st, d, src);
+    hipLaunchKernelGGL(k, grid, block, lds, st, d, src);
 }
 
 // Liquid chosen from the descriptor: a reactive solve is always Cochran-Chan.

@@ -66,9 +66,24 @@ struct Desc {
     // reactive liquid: Gamma0 and c_v (temperature, Eq. (5)); Arrhenius C, Ta
     // and heat of reaction Q (Eq. (6), Table 3)
     double cG0, rxcv, rxC, rxTa, rxQ;
-    // a recording step (fused averages): per segment s, 3 * nx column sums of
-    // pressure, density and x momentum at diag + 3 * nx * s; nullptr otherwise
+    // A recording step (diagnostics summed in the store epilogue); each
+    // pointer is nullptr when that quantity is not recorded.
+    //  diag: per segment s, 3 * nx column sums of pressure, density and x
+    //        momentum at diag + 3 * nx * s (transverse averages);
+    //  dint: per workgroup (strip bx, segment by), the sums of the nc stored
+    //        planes at dint + nc * (by * nstrips + bx) (domain integrals);
+    //  dhist: the liquid mass z2 rho2 dx dy of the stored cells per bin of
+    //        field hfield (MF_P, MF_RHO or MF_QDOT) over the hbins + 1
+    //        ascending edges hedges, accumulated into dhist (zeroed before
+    //        the step).
+    //  hlo, hidn: lo and 1/dn of the edges 10^(lo + k dn), for a first guess
+    //        of a cell's bin.
     double *diag;
+    double *dint;
+    double *dhist;
+    const double *hedges;
+    int hbins, hfield;
+    float hlo, hidn;
 };
 
 // Host helpers shared by the solver and the server (meso_api.hip).
@@ -123,6 +138,14 @@ hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const d
 // from the segment sums a recording step left at d.diag; NaN if the step was
 // skipped.
 hipError_t launch_diag_row(const Desc &d, double *row, hipStream_t st);
+// One row of a fused-integrals record: the nc integrals (cell area times the
+// workgroup sums at d.dint, added in workgroup order); NaN if skipped.
+hipError_t launch_int_row(const Desc &d, double *row, hipStream_t st);
+// A fused-histogram row: zeroed before the recording step (hist_clear), then
+// divided by m_ref * dn, or NaN if the step was skipped (hist_finish).
+hipError_t launch_hist_clear(double *row, int nbins, hipStream_t st);
+hipError_t launch_hist_finish(const Desc &d, double *row, int nbins, double m_ref_dn,
+                              hipStream_t st);
 // Many solves at once: descs/tiles are device arrays; tiles[b] = (solve index
 // into descs, strip, segment, unused); every tile of one launch belongs to a
 // solve whose liquid is `eos` and which has `nc` conserved planes (7: reactive).

@@ -174,30 +174,6 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(Desc d, int src_idx, i
     block_cfl_commit((double)smax, bad, d.ctl, slot);
 }
 
-// Liquid temperature of Eq. (5) (T_ref = 0, constant Gamma_0 and c_v) of a
-// cell of a reactive Cochran-Chan liquid, evaluated in FP64.
-__device__ __forceinline__ double liquid_temperature(const Mix<double> &m, const Rx<double> &x,
-                                                     const double q[7]) {
-    double w[7], r, rc2;
-    cons_to_prim<double, false, 7>(m, q, w, r, rc2);
-    const double rho2 = q[1] / (1.0 - q[5]);
-    const double v = m.rho0 / rho2;
-    double vc, vd;
-    Ar<double, false>::pw(v, m.C, m.D, vc, vd);
-    const double pref = m.A * vc - m.B * vd;
-    return (w[4] - pref) / ((rho2 * x.G0) * x.cv);
-}
-
-// Volumetric heat-release rate -z2 rho2 K Q of the reactive liquid (Sec. 4.5)
-// in GW/m^3; 0 without reactant or at T2 <= 0.
-__device__ __forceinline__ double heat_release(const Mix<double> &m, const Rx<double> &x,
-                                               const double q[7]) {
-    if (!(q[6] > 0.0)) return 0.0;
-    const double T = liquid_temperature(m, x, q);
-    if (!(T > 0.0)) return 0.0;
-    return ((q[6] * x.C) * exp(-x.Ta / T) * x.Q) * 1.0e-9;
-}
-
 // One field of the state as dense FP64 (conserved planes are widened, derived
 // fields 6-10 use the closure in the storage type, the reaction fields 12-14
 // the FP64 closure of the widened state).
@@ -387,6 +363,36 @@ __global__ void diag_row_kernel(const Control *ctl, const double *part, int nseg
     row[2 * nx + i] = sm / sr;
 }
 
+// One row of a fused-integrals record: block c adds plane c's workgroup sums
+// (thread i takes workgroups i, i + 256, ... in order, then a fixed halving
+// tree) and multiplies by the cell area; a skipped step gives NaN.
+__global__ __launch_bounds__(256) void int_row_kernel(const Control *ctl, const double *part,
+                                                      int ntiles, int nc, double area,
+                                                      double *row) {
+    __shared__ double red[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    if (ctl->skip) {
+        if (t == 0) row[c] = __longlong_as_double(0x7FF8000000000000LL);
+        return;
+    }
+    double s = 0.0;
+    for (int g = t; g < ntiles; g += 256) s = s + part[(long long)g * nc + c];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] = red[t] + red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) row[c] = red[0] * area;
+}
+
+// A fused-histogram row after its step: the bin masses divided by m_ref * dn
+// (as mf_log_histogram does), or NaN if the step was skipped.
+__global__ void hist_row_kernel(const Control *ctl, double *row, int n, double s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) row[k] = ctl->skip ? __longlong_as_double(0x7FF8000000000000LL) : row[k] / s;
+}
+
 constexpr int kMaxBins = 1024;
 
 // Mass-weighted histogram over log-spaced bins: bin a (edges[a] <= v <
@@ -564,6 +570,24 @@ hipError_t launch_columns(const Desc &d, int prec, int src, double *out, hipStre
 hipError_t launch_diag_row(const Desc &d, double *row, hipStream_t st) {
     hipLaunchKernelGGL(diag_row_kernel, dim3((d.nx + 255) / 256), dim3(256), 0, st, d.ctl, d.diag,
                        d.nsegs, d.nx, d.ny, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_int_row(const Desc &d, double *row, hipStream_t st) {
+    hipLaunchKernelGGL(int_row_kernel, dim3(d.nc), dim3(256), 0, st, d.ctl, d.dint,
+                       d.nstrips * d.nsegs, d.nc, d.dx * d.dy, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_clear(double *row, int nbins, hipStream_t st) {
+    hipLaunchKernelGGL(fill_kernel, dim3((nbins + 255) / 256), dim3(256), 0, st, row, nbins, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_finish(const Desc &d, double *row, int nbins, double m_ref_dn,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(hist_row_kernel, dim3((nbins + 255) / 256), dim3(256), 0, st, d.ctl, row,
+                       nbins, m_ref_dn);
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ EXPORTS = ["mf_workspace_bytes", "mf_create", "mf_set_primitive", "mf_set_conser
            "mf_server_poll", "mf_server_finished", "mf_server_result", "mf_server_drain",
            "mf_server_get_stats",
            "mf_server_destroy", "mf_stream_copy", "mf_integrals_noalloc",
-           "mf_record_averages", "mf_recorded_rows"]
+           "mf_record_averages", "mf_recorded_rows", "mf_record_integrals",
+           "mf_record_histogram", "mf_recorded_counts"]
 
 
 class MesoError(RuntimeError):
@@ -142,6 +143,10 @@ def load_library():
         "mf_integrals_noalloc": (C.c_int32, [P, D, C.c_size_t]),
         "mf_record_averages": (C.c_int32, [P, P, C.c_int64]),
         "mf_recorded_rows": (C.c_int32, [P, I64]),
+        "mf_record_integrals": (C.c_int32, [P, P, C.c_int64]),
+        "mf_record_histogram": (C.c_int32, [P, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                            C.c_double, P, C.c_int64]),
+        "mf_recorded_counts": (C.c_int32, [P, I64]),
         "mf_log_histogram": (C.c_int32, [P, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                          C.c_double, D]),
         "mf_destroy": (C.c_int32, [P]),
@@ -327,6 +332,28 @@ class Solver:
         n = C.c_int64()
         _chk("mf_recorded_rows", self._lib.mf_recorded_rows(self._h, C.byref(n)))
         return n.value
+
+    def record_integrals(self, rows_ptr: int, max_rows: int) -> None:
+        """Record fused domain integrals (rows of `nplanes` doubles, as
+        `integrals()`) into device memory at `rows_ptr`; 0 stops."""
+        _chk("mf_record_integrals", self._lib.mf_record_integrals(
+            self._h, C.c_void_p(rows_ptr or None), int(max_rows)))
+
+    def record_histogram(self, field, lo: float, dn: float, nbins: int, m_ref: float,
+                         rows_ptr: int, max_rows: int) -> None:
+        """Record the fused mass-weighted PDF of `field` (rows of `nbins`
+        doubles, as `log_histogram()`) into device memory at `rows_ptr`;
+        rows_ptr 0 stops."""
+        f = FIELDS[field] if isinstance(field, str) else int(field)
+        _chk("mf_record_histogram", self._lib.mf_record_histogram(
+            self._h, f, float(lo), float(dn), int(nbins), float(m_ref),
+            C.c_void_p(rows_ptr or None), int(max_rows)))
+
+    def recorded_counts(self):
+        """Rows enqueued by the averages, integrals and histogram records."""
+        n = (C.c_int64 * 3)()
+        _chk("mf_recorded_counts", self._lib.mf_recorded_counts(self._h, n))
+        return tuple(int(v) for v in n)
 
     def enable_timing(self, on: bool = True) -> None:
         _chk("mf_enable_timing", self._lib.mf_enable_timing(self._h, 1 if on else 0))

@@ -131,6 +131,9 @@ def test_null_handles_are_rejected():
     assert lib.mf_integrals_noalloc(None, None, 6) == -1
     assert lib.mf_record_averages(None, None, 1) == -1
     assert lib.mf_recorded_rows(None, None) == -1
+    assert lib.mf_record_integrals(None, None, 1) == -1
+    assert lib.mf_record_histogram(None, 9, 0.0, 0.1, 10, 1.0, None, 1) == -1
+    assert lib.mf_recorded_counts(None, None) == -1
     assert lib.mf_create(None, None, None, None, 0, None, None) == -1
     n = C.c_int32()
     assert lib.mf_server_finished(None, None, 0, C.byref(n)) == -1

@@ -1,0 +1,292 @@
+"""Fused diagnostics recorded in the step's store epilogue: the domain
+integrals (with the remaining reactant mass M_2,r of Eq. (10)) and the
+mass-weighted log-binned PDF of Sec. 4.5, recorded every step while the step
+writes the state, against the separate diagnostics of the same state
+(mf_integrals, mf_log_histogram) and the oracle's.
+
+Tolerances follow from the summation orders: an integral is a sum of N cell
+values that the separate pass and the oracle add column by column and the
+recording step workgroup by workgroup, so two orders agree to 2 N u of the sum
+of magnitudes (u = 2^-53); a PDF bin is a sum of up to N positive cell masses
+(2 N u relative).  A bin decision is taken in FP64 on both sides, but the
+recording kernels of the fast modes fuse multiply-adds in the closure and the
+heat-release rate goes through exp, so a cell within rounding of a bin edge
+may fall on either side of it; the PDF check allows exactly that mass to move
+across that edge and holds every other bin to 2 N u."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_05727_amd import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1905_05727_amd import meso  # noqa: E402
+
+U_ROUND = 2.0 ** -53
+BCO = {"transmissive": oracle.TRANSMISSIVE, "periodic": oracle.PERIODIC}
+LIM = {"vanleer": oracle.VANLEER, "minmod": oracle.MINMOD}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_of(sc):
+    bc = [BCO[b] for b in sc.bc]
+    P = oracle.Problem(sc.nx, sc.ny, sc.dx, sc.dy, gamma1=sc.gamma1, pinf1=sc.pinf1,
+                       gamma2=sc.gamma2, pinf2=sc.pinf2, cfl=sc.cfl, zeps=sc.zeps,
+                       limiter=LIM[sc.limiter], bc_xlo=bc[0], bc_xhi=bc[1], bc_ylo=bc[2],
+                       bc_yhi=bc[3], eos2=sc.eos2, cc=sc.cc, reactive=int(sc.reactive),
+                       rx=sc.rx)
+    o = oracle.Oracle(P)
+    o.set_primitive(sc.prim)
+    return o
+
+
+def bubble(nx, ny):
+    return S.single_bubble(nx=nx, ny=ny, radius=min(nx, ny) / 5, centre=(nx * 0.55, ny / 2),
+                           shock_x=nx * 0.3)
+
+
+def hot_bubble(nx=240, ny=120):
+    """A cavity in reacting nitromethane hit by the 7.81 GPa shock of Sec. 4."""
+    return S.single_bubble(nx=nx, ny=ny, dx=1e-6, radius=ny / 5, centre=(nx * 0.55, ny / 2),
+                           shock_x=nx * 0.3, liquid="nm", p_shock=7.81e9, reactive=True)
+
+
+def roofline_crop(rows=256):
+    """The first `rows` rows of the 8192^2 roofline field, in the launch
+    configuration of every full-width grid (33 strips, several segments)."""
+    sc = S.roofline_8192()
+    sc.prim = np.ascontiguousarray(sc.prim[:, :rows, :])
+    sc.ny = rows
+    return sc
+
+
+def check_integrals(row, ref, U, area, what):
+    """row, ref: integrals of the state U from two summation orders."""
+    n = U.shape[1] * U.shape[2]
+    mag = np.abs(U).reshape(U.shape[0], -1).sum(axis=1) * area
+    d = np.abs(row - ref)
+    say(f"{what}: integral differences / magnitude {np.array2string(d / mag, precision=2)}")
+    assert np.all(d <= 2.0 * n * U_ROUND * mag * 1.0000001 + 1e-300), what
+
+
+def check_pdf(f, ref, v, w, edges, what, rel=1e-13):
+    """f, ref: the same PDF of one state from two passes (bin masses over
+    m_ref dn).  v: every cell's field value, w: its share z2 rho2 dx dy /
+    (m_ref dn).  Both passes evaluate the field in FP64, but not necessarily
+    with the same operations, so a cell within rounding (rel) of an edge may
+    fall on either side of it: the cumulative mass below each edge e may
+    differ by the share of the cells near e (and near the lowest edge, which
+    decides whether a cell is counted at all), plus the 2 N u of two
+    summation orders; a bin with no such cell at either edge agrees to 2 N u
+    relative, occupancy included."""
+    nb = f.size
+    v, w = v.ravel(), w.ravel()
+    k = np.searchsorted(edges, v)
+    amb = np.zeros(nb + 1)
+    for e in (k - 1, k):
+        ok = (e >= 0) & (e <= nb)
+        near = ok.copy()
+        near[ok] = np.abs(v[ok] - edges[e[ok]]) <= rel * np.abs(v[ok])
+        np.add.at(amb, e[near], w[near])
+    tol = 2.0 * v.size * U_ROUND
+    cf = np.concatenate([[0.0], np.cumsum(f)])
+    cr = np.concatenate([[0.0], np.cumsum(ref)])
+    allowed = amb + np.where(np.arange(nb + 1) > 0, amb[0], 0.0) + tol * cr[-1]
+    d = np.abs(cf - cr)
+    clean = (amb[:-1] == 0) & (amb[1:] == 0)
+    worst = float(np.max(np.abs(f[clean] - ref[clean]) / np.maximum(ref[clean], 1e-300),
+                         initial=0.0))
+    say(f"{what}: {np.count_nonzero(ref)} bins occupied, {np.count_nonzero(amb)} edges with "
+        f"cells within rounding, largest cumulative difference {d.max():.2e}, largest "
+        f"relative difference of the other bins {worst:.2e}")
+    assert np.all(d <= allowed * 1.0000001), what
+    assert np.array_equal(f[clean] > 0, ref[clean] > 0), what
+    np.testing.assert_allclose(f[clean], ref[clean], rtol=tol, atol=0, err_msg=what)
+
+
+def check_averages(row, ref, U, what):
+    """row, ref: (3, nx) p_bar, rho_bar, u_bar of U in two summation orders."""
+    k = 2.0 * U.shape[1] * U_ROUND
+    srho = (U[0] + U[1]).sum(axis=0)
+    smu = np.abs(U[2]).sum(axis=0)
+    assert np.all(np.abs(row[0] - ref[0]) <= k * ref[0] * 1.0000001 + 1e-300), what
+    assert np.all(np.abs(row[1] - ref[1]) <= k * ref[1] * 1.0000001), what
+    tol_u = (k * smu + np.abs(ref[2]) * k * srho) / srho + 2 * U_ROUND * np.abs(ref[2])
+    assert np.all(np.abs(row[2] - ref[2]) <= tol_u * 1.0000001 + 1e-300), what
+
+
+def dev_rows(*shape):
+    return torch.full(shape, -1.0, dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64_fast", "fp32_fp64acc", "fp32"])
+def test_recorded_integrals_and_pdf_match_separate_passes(prec):
+    """All three records at once on a 300 x 140 bubble (several segments per
+    strip), 12 recorded steps and two more past max_rows: the state bit for
+    bit that of a run without recording; every row against the separate
+    diagnostics of the state after that step; the last rows against the
+    oracle's diagnostics of the same state."""
+    sc = bubble(300, 140)
+    nsteps, nbins, lo, dn = 12, 300, 4.0, 0.02
+    say(f"case: recorded averages + integrals + pressure PDF 300x140, {prec}")
+    area = sc.dx * sc.dy
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        m_ref = float(s.integrals()[1])
+    avg = dev_rows(nsteps + 2, 3, sc.nx)
+    itg = dev_rows(nsteps + 2, 6)
+    pdf = dev_rows(nsteps + 2, nbins)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.record_averages(avg.data_ptr(), nsteps)
+        s.record_integrals(itg.data_ptr(), nsteps)
+        s.record_histogram("p", lo, dn, nbins, m_ref, pdf.data_ptr(), nsteps)
+        s.run_steps(nsteps + 2)
+        s.sync()
+        assert s.recorded_counts() == (nsteps, nsteps, nsteps)
+        assert s.recorded_rows() == nsteps
+        U_rec = s.read_conserved()
+    A, I, F = avg.cpu().numpy(), itg.cpu().numpy(), pdf.cpu().numpy()
+    for X in (A, I, F):
+        assert np.all(X[nsteps:] == -1.0)
+    o = oracle_of(sc)
+    edges = oracle.log_edges(lo, dn, nbins)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        for r in range(nsteps + 2):
+            s.run_steps(1)
+            if r < nsteps:
+                U = s.read_conserved()
+                check_averages(A[r], np.stack(s.y_averages()), U, f"{prec} averages row {r}")
+                check_integrals(I[r], s.integrals(), U, area, f"{prec} integrals row {r}")
+                o.U[...] = U
+                check_pdf(F[r], s.log_histogram("p", lo, dn, nbins, m_ref),
+                          o.primitive()["p"], U[1] * area / (m_ref * dn), edges,
+                          f"{prec} p PDF row {r}")
+        U = s.read_conserved()
+    assert np.array_equal(U_rec, U), "state changed by recording"
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(nsteps)
+        Un = s.read_conserved()
+    o = oracle_of(sc)
+    o.U[...] = Un
+    check_integrals(I[nsteps - 1], o.integrals(), Un, area, f"{prec} last integrals vs oracle")
+    check_pdf(F[nsteps - 1], o.log_histogram(9, lo, dn, nbins, m_ref), o.primitive()["p"],
+              Un[1] * area / (m_ref * dn), edges, f"{prec} last p PDF vs oracle")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_recorded_integrals_alone(prec):
+    """Integrals recorded without the other records (40 x 9 and 33 x 49: a
+    single ragged strip, segments of a few rows), every row against
+    mf_integrals of the state after that step."""
+    for nx, ny in ((40, 9), (33, 49)):
+        sc = bubble(nx, ny)
+        say(f"case: recorded integrals alone {nx}x{ny}, {prec}")
+        itg = dev_rows(8, 6)
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            s.record_integrals(itg.data_ptr(), 8)
+            s.run_steps(8)
+            s.sync()
+            assert s.recorded_counts() == (0, 8, 0)
+        I = itg.cpu().numpy()
+        with meso.Solver.from_scenario(sc, precision=prec) as s:
+            for r in range(8):
+                s.run_steps(1)
+                check_integrals(I[r], s.integrals(), s.read_conserved(), sc.dx * sc.dy,
+                                f"{nx}x{ny} row {r}")
+
+
+@pytest.mark.parametrize("prec", ["fp64_fast", "fp32_fp64acc"])
+def test_recorded_pdf_full_width_and_skipped_steps(prec):
+    """An 8192 x 256 crop of the roofline field in its launch configuration:
+    integrals and the density PDF (no averages) recorded over 200 steps, the
+    last row against the oracle's diagnostics of the state; then run-to-time
+    past its end, where the steps the device skips record NaN rows, and
+    recording stops."""
+    sc = roofline_crop()
+    nbins, lo, dn = 400, -1.0, 0.01
+    n = sc.nx * sc.ny
+    area = sc.dx * sc.dy
+    say(f"case: recorded integrals + density PDF 8192x256, {prec}, then run-to-time")
+    itg = dev_rows(230, 6)
+    pdf = dev_rows(230, nbins)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        m_ref = float(s.integrals()[1])
+        s.record_integrals(itg.data_ptr(), 200)
+        s.record_histogram("rho", lo, dn, nbins, m_ref, pdf.data_ptr(), 200)
+        s.run_steps(200)
+        U = s.read_conserved()
+        t200, _, _ = s.time()
+        I, F = itg.cpu().numpy(), pdf.cpu().numpy()
+        o = oracle_of(sc)
+        o.U[...] = U
+        check_integrals(I[199], o.integrals(), U, area, "8192x256 row 199 integrals vs oracle")
+        fo = o.log_histogram(6, lo, dn, nbins, m_ref)
+        assert np.count_nonzero(fo) > 5
+        check_pdf(F[199], fo, U[0] + U[1], U[1] * area / (m_ref * dn),
+                  oracle.log_edges(lo, dn, nbins), "8192x256 row 199 density PDF vs oracle")
+        s.record_integrals(itg.data_ptr(), 30)
+        s.record_histogram("rho", lo, dn, nbins, m_ref, pdf.data_ptr(), 30)
+        taken = s.run_to_time(t200 + 5.5e-9)
+        ci = s.recorded_counts()
+        assert ci[0] == 0 and ci[1] == ci[2]
+        k = ci[1]
+        assert 1 <= taken < k <= 30, (taken, k)
+        I, F = itg.cpu().numpy(), pdf.cpu().numpy()
+        for X in (I, F):
+            assert np.all(np.isfinite(X[:taken])) and np.all(np.isnan(X[taken:k]))
+        assert np.all(np.isfinite(I[k:30]))   # rows past the record: the earlier run's
+        s.record_integrals(0, 0)
+        s.record_histogram("rho", lo, dn, nbins, m_ref, 0, 0)
+        s.run_steps(1)
+        s.sync()
+        assert s.recorded_counts() == ci
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64_fast", "fp32_fp64acc"])
+def test_recorded_reactant_mass_and_qdot_pdf(prec):
+    """Reacting nitromethane bubble (Eqs. (5), (6)): from step 140 on, 20
+    recorded steps of the integrals (M_2,r of Eq. (10) in the last place) and
+    the q-dot PDF of Sec. 4.5 (400 bins of 0.02 decades over 10^2 - 10^10
+    GW/m^3), each against the separate diagnostics of the state after that
+    step; the last ones against the oracle's."""
+    sc = hot_bubble()
+    nbins, lo, dn = 400, 2.0, 0.02
+    area = sc.dx * sc.dy
+    say(f"case: recorded reactant mass + q-dot PDF 240x120, {prec}")
+    itg = dev_rows(20, 7)
+    pdf = dev_rows(20, nbins)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        m_tot = float(s.integrals()[1])
+        s.run_steps(140)
+        s.record_integrals(itg.data_ptr(), 20)
+        s.record_histogram("qdot", lo, dn, nbins, m_tot, pdf.data_ptr(), 20)
+        s.run_steps(20)
+        s.sync()
+        assert s.recorded_counts() == (0, 20, 20)
+        U_rec = s.read_conserved()
+    I, F = itg.cpu().numpy(), pdf.cpu().numpy()
+    edges = oracle.log_edges(lo, dn, nbins)
+    with meso.Solver.from_scenario(sc, precision=prec) as s:
+        s.run_steps(140)
+        for r in range(20):
+            s.run_steps(1)
+            U = s.read_conserved()
+            qd = s.read_field("qdot")
+            check_integrals(I[r], s.integrals(), U, area, f"{prec} integrals row {r}")
+            check_pdf(F[r], s.log_histogram("qdot", lo, dn, nbins, m_tot), qd,
+                      U[1] * area / (m_tot * dn), edges, f"{prec} q-dot PDF row {r}",
+                      rel=1e-12)
+    assert np.array_equal(U_rec, U), "state changed by recording"
+    assert F[19].sum() > 0.0 and np.all(I[:, 6] > 0.0)
+    o = oracle_of(sc)
+    o.U[...] = U
+    check_integrals(I[19], o.integrals(), U, area, f"{prec} last integrals vs oracle")
+    check_pdf(F[19], o.log_histogram(14, lo, dn, nbins, m_tot), qd, U[1] * area / (m_tot * dn),
+              edges, f"{prec} last q-dot PDF vs oracle", rel=1e-12)
