@@ -346,9 +346,33 @@ template <class R, int NC> __device__ __forceinline__ void side_finish(Side<R, N
     }
 }
 
-template <class R, int FAST, int NC>
+// Star-state flux F* = F + S (U* - U) of side k with wave speed S, contact
+// speed S*.  KV (the fast FP64 and FP32 kernels): rearranged so that every
+// component carried with the flow (partial densities, tangential momentum,
+// reactant mass, the volume flux of z) is kv U with kv = d S* / (S - S*),
+// d = S - u, the star state's volume flux velocity (0 exactly at S* = 0);
+// normal momentum p + rho (d (S* - u) + kv S*), energy kv E + p u + S (S* - u)
+// (chi rho S* + p / (S - S*)), chi = d / (S - S*).  Equal in exact arithmetic
+// to the direct form, with fewer operations; the FP32-bulk kernel measured
+// slower with it and keeps the direct form.
+template <class R, int FAST, int NC, bool KV = false>
 __device__ __forceinline__ void star_flux(const Side<R, NC> &k, R S, R Ss, R out[NC + 1]) {
     const R d = S - k.un;
+    if constexpr (FAST != 0 && KV) {
+        const R inv = Ar<R, FAST>::rcp(S - Ss);
+        const R chi = d * inv;
+        const R kv = (d * Ss) * inv;
+        const R su = Ss - k.un;
+        out[0] = kv * k.U[0];
+        out[1] = kv * k.U[1];
+        out[2] = k.p + k.rho * (d * su + kv * Ss);
+        out[3] = kv * k.U[3];
+        out[4] = kv * k.E + k.p * k.un + S * (su * (chi * (k.rho * Ss) + k.p * inv));
+        out[5] = kv;
+        out[6] = k.z;
+        if constexpr (NC == 7) out[7] = kv * k.U[5];
+        return;
+    }
     R chi;
     R us[5];
     if constexpr (FAST) {   // chi/d = 1/(S - S*): one reciprocal for the whole star state
@@ -444,7 +468,7 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
 #pragma unroll
                 for (int c = 0; c < NC - 1; ++c) K.F[c] = useL ? L.F[c] : Rs.F[c];
             }
-            star_flux<R, FAST, NC>(K, useL ? SL : SR, Ss, st);
+            star_flux<R, FAST, NC, !kTieAverage>(K, useL ? SL : SR, Ss, st);
         };
         if constexpr (kUniform) {
             const unsigned long long act = __builtin_amdgcn_read_exec();   // lanes on this path
@@ -452,11 +476,11 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
             if (onL == act) {
                 Side<R, NC> K = L;
                 finish(K);
-                star_flux<R, FAST, NC>(K, SL, Ss, st);
+                star_flux<R, FAST, NC, !kTieAverage>(K, SL, Ss, st);
             } else if (onL == 0) {
                 Side<R, NC> K = Rs;
                 finish(K);
-                star_flux<R, FAST, NC>(K, SR, Ss, st);
+                star_flux<R, FAST, NC, !kTieAverage>(K, SR, Ss, st);
             } else {
                 select_side();
             }
@@ -470,8 +494,8 @@ __device__ __forceinline__ void hllc(const Mix<R> &m, const R wL[NC], const R wR
         finish(KL);
         finish(KR);
         R a[NC + 1], b[NC + 1];
-        star_flux<R, FAST, NC>(KL, SL, Ss, a);
-        star_flux<R, FAST, NC>(KR, SR, Ss, b);
+        star_flux<R, FAST, NC, !kTieAverage>(KL, SL, Ss, a);
+        star_flux<R, FAST, NC, !kTieAverage>(KR, SR, Ss, b);
 #pragma unroll
         for (int c = 0; c < NC + 1; ++c) st[c] = R(0.5) * (a[c] + b[c]);
     }
