@@ -290,3 +290,47 @@ def test_recorded_reactant_mass_and_qdot_pdf(prec):
     check_integrals(I[19], o.integrals(), U, area, f"{prec} last integrals vs oracle")
     check_pdf(F[19], o.log_histogram(14, lo, dn, nbins, m_tot), qd, U[1] * area / (m_tot * dn),
               edges, f"{prec} last q-dot PDF vs oracle", rel=1e-12)
+
+
+def test_recorded_pdf_fine_bins_and_argument_checks():
+    """1024 bins of 1e-6 decades (2.3e-6 relative) over a periodic water
+    field whose pressure varies by 0.1 % around 1e5 Pa: the FP32 logarithm's
+    first guess of a bin is then off by up to a few bins, and the FP64 edge
+    comparisons must walk it to the bins of mf_log_histogram's search.  Then
+    the argument checks of the recording calls."""
+    nx, ny = 300, 140
+    rng = np.random.default_rng(7)
+    prim = S.uniform_state(nx, ny, dx=1e-3)
+    prim[3] = rng.uniform(-1e-5, 1e-5, (ny, nx))   # rho c du ~ 15 Pa: pressures stay in range
+    prim[4] = rng.uniform(-1e-5, 1e-5, (ny, nx))
+    prim[5] = 1e5 * (1.0 + 1e-3 * rng.uniform(-1.0, 1.0, (ny, nx)))
+    sc = S.Scenario("fine pressure bins", nx, ny, 1e-3, 1e-3, prim, bc=("periodic",) * 4)
+    nbins, lo, dn = 1024, 5.0 - 512e-6, 1e-6
+    say("case: recorded pressure PDF with 1e-6-decade bins, 300x140 fp64_fast")
+    pdf = dev_rows(4, nbins)
+    with meso.Solver.from_scenario(sc, precision="fp64_fast") as s:
+        m_ref = float(s.integrals()[1])
+        s.run_steps(5)
+        s.record_histogram("p", lo, dn, nbins, m_ref, pdf.data_ptr(), 4)
+        s.run_steps(4)
+        U = s.read_conserved()
+        f_sep = s.log_histogram("p", lo, dn, nbins, m_ref)
+        lib, h = s._lib, s._h
+        for args in ((9, lo, dn, 0, m_ref), (9, lo, dn, 1025, m_ref), (9, lo, 0.0, 10, m_ref),
+                     (9, lo, dn, 10, 0.0), (14, lo, dn, 10, m_ref), (9, float("nan"), dn, 10,
+                                                                     m_ref)):
+            assert lib.mf_record_histogram(h, *args, pdf.data_ptr(), 4) == -1, args
+        assert lib.mf_record_histogram(h, 9, lo, dn, 10, m_ref, pdf.data_ptr(), 0) == -1
+        assert lib.mf_record_histogram(h, 9, lo, dn, 10, m_ref, pdf.data_ptr() + 4, 1) == -1
+        assert lib.mf_record_integrals(h, pdf.data_ptr(), 0) == -1
+        assert lib.mf_record_integrals(h, pdf.data_ptr() + 4, 1) == -1
+    F = pdf.cpu().numpy()
+    o = oracle_of(sc)
+    o.U[...] = U
+    w = U[1] * sc.dx * sc.dy / (m_ref * dn)
+    edges = oracle.log_edges(lo, dn, nbins)
+    assert np.count_nonzero(f_sep) > 200
+    check_pdf(F[3], f_sep, o.primitive()["p"], w, edges, "fine bins vs mf_log_histogram")
+    with meso.Solver.from_scenario(sc, precision="fp64_fast", fused=False) as s:
+        assert s._lib.mf_record_integrals(s._h, pdf.data_ptr(), 1) == -1
+        assert s._lib.mf_record_histogram(s._h, 9, lo, dn, 10, m_ref, pdf.data_ptr(), 1) == -1
