@@ -719,8 +719,6 @@ __device__ __forceinline__ void react(S q[7], const Mix<S> &m, const Rx<S> &x, S
     q[6] = q[1] * lam_new;
 }
 
-// Pointwise stage and CFL contribution of one updated cell (U order): the z1
-// clamp, the second half of the reaction (NC = 7), then the signal speed.
 // Liquid temperature of Eq. (5) (T_ref = 0, constant Gamma_0 and c_v) of a
 // cell of a reactive Cochran-Chan liquid, evaluated in FP64.
 __device__ __forceinline__ double liquid_temperature(const Mix<double> &m, const Rx<double> &x,
@@ -745,6 +743,8 @@ __device__ __forceinline__ double heat_release(const Mix<double> &m, const Rx<do
     return ((q[6] * x.C) * exp(-x.Ta / T) * x.Q) * 1.0e-9;
 }
 
+// Pointwise stage and CFL contribution of one updated cell (U order): the z1
+// clamp, the second half of the reaction (NC = 7), then the signal speed.
 template <class S, int FAST, int NC, int EOS>
 __device__ __forceinline__ void epilogue(S q[NC], const Mix<S> &ms, const Rx<S> &rx, S hdt,
                                          S zlo, S zhi, S idx, S idy, S &smax, int &bad) {
