@@ -545,6 +545,10 @@ template <class S, class R, int FAST, int LIM, int NC, int EOS>
 __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R hl,
                                       const Mix<S> &ms, const Mix<R> &mr,
                                       R (*sWF)[kThreads], R (*sH)[kThreads]) {
+    // the barrier-bound x sweep issues ahead of the other wave on the SIMD
+    // (another workgroup's barrier-free y sweep), so the workgroup reaches
+    // its barriers sooner
+    __builtin_amdgcn_s_setprio(2);
     S w[NC], r, rc2;
     cons_to_prim<S, FAST, NC, EOS>(ms, q, w, r, rc2);
     R wr[NC];
@@ -587,6 +591,7 @@ __device__ __forceinline__ void x_row(const S q[NC], S qo[NC], int t, S lam, R h
         for (int c = 0; c < NC; ++c) qo[c] = q[c];
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // x_row for the batched kernel: idle (uniform per wave) means the wave lies
