@@ -52,7 +52,7 @@ def kernel_source_hash() -> str:
     comment edit does not invalidate a counter summary of the same code)."""
     h = hashlib.sha256()
     for f in ("meso_device.h", "meso_kernels.hip", "meso_kernels_fast.hip",
-              "meso_kernels_fast64.hip",
+              "meso_kernels_fast64.hip", "meso_kernels_fp32.hip",
               "meso_kernels_react.hip", "meso_kernels_react_fast.hip", "meso_internal.h",
               "meso_api.hip"):
         text = open(os.path.join(ROOT, "paper_1905_05727_amd", "csrc", f)).read()

@@ -1,11 +1,13 @@
 """Build step of the HIP library (hipcc, gfx950).
 
-The shared library libmeso.so is built in-tree next to this file from eight
+The shared library libmeso.so is built in-tree next to this file from nine
 translation units, compiled in parallel.  The FP64 kernels and the host code
 are compiled with -ffp-contract=off (every operation rounds separately, so
-the FP64 mode follows the arithmetic contract bit for bit); the FP32-bulk /
-FP32 and fast-FP64 kernels with -ffp-contract=fast (fused multiply-adds).  No fast-math anywhere, and
-packed FP32 instructions are disabled (-packed-fp32-ops).
+the FP64 mode follows the arithmetic contract bit for bit); the FP32-bulk,
+FP32 and fast-FP64 kernels with -ffp-contract=fast (fused multiply-adds).
+The FP64, fast-FP64 and FP32 kernels take the ILP-maximising instruction
+scheduler.  No fast-math anywhere, and packed FP32 instructions are disabled
+(-packed-fp32-ops).
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ ARCH = os.environ.get("MESO_OFFLOAD_ARCH", "gfx950")
 # 4-wave occupancy limits.
 UNITS = [("meso_kernels.hip", "off", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
          ("meso_kernels_fast.hip", "fast", []),
+         ("meso_kernels_fp32.hip", "fast", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
          ("meso_kernels_react.hip", "off", []), ("meso_kernels_react_fast.hip", "fast", []),
          ("meso_kernels_fast64.hip", "fast", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
          ("meso_stream.hip", "off", []),

@@ -152,11 +152,16 @@ hipError_t launch_hist_finish(const Desc &d, double *row, int nbins, double m_re
 hipError_t launch_batched_dt(const Desc *descs, int n, hipStream_t st);
 hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles, int prec,
                                int lim, int eos, int nc, hipStream_t st);
-// The FP32-bulk and FP32 instantiations (meso_kernels_fast.hip).
-hipError_t launch_step_fast(const Desc &d, int prec, int lim, int mode, int final_pass, int src,
+// The FP32-bulk instantiations (meso_kernels_fast.hip) and the FP32 ones
+// (meso_kernels_fp32.hip), inert liquids.
+hipError_t launch_step_fast(const Desc &d, int lim, int mode, int final_pass, int src,
                             hipStream_t st);
-hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int prec,
-                                    int lim, int eos, hipStream_t st);
+hipError_t launch_batched_step_fast(const Desc *descs, const int4 *tiles, int ntiles, int lim,
+                                    int eos, hipStream_t st);
+hipError_t launch_step_fp32(const Desc &d, int lim, int mode, int final_pass, int src,
+                            hipStream_t st);
+hipError_t launch_batched_step_fp32(const Desc *descs, const int4 *tiles, int ntiles, int lim,
+                                    int eos, hipStream_t st);
 // Reactive solves (seven components): FP64 (meso_kernels_react.hip) and the
 // FP32-bulk / FP32 modes (meso_kernels_react_fast.hip).
 hipError_t launch_step_react(const Desc &d, int prec, int lim, int mode, int final_pass, int src,

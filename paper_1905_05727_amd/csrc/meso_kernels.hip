@@ -523,7 +523,8 @@ hipError_t launch_step(const Desc &d, int prec, int lim, int mode, int final_pas
                        hipStream_t st) {
     if (prec == kP64F) return launch_step_fast64(d, lim, mode, final_pass, src, st);
     if (d.nc == 7) return launch_step_react(d, prec, lim, mode, final_pass, src, st);
-    if (prec != kP64) return launch_step_fast(d, prec, lim, mode, final_pass, src, st);
+    if (prec == kP32) return launch_step_fp32(d, lim, mode, final_pass, src, st);
+    if (prec == kPMix) return launch_step_fast(d, lim, mode, final_pass, src, st);
     if (lim == 1) launch_step_variants<double, double, false, 1, 6>(d, mode, final_pass, src, st);
     else launch_step_variants<double, double, false, 0, 6>(d, mode, final_pass, src, st);
     return hipGetLastError();
@@ -540,7 +541,8 @@ hipError_t launch_batched_step(const Desc *descs, const int4 *tiles, int ntiles,
     if (ntiles <= 0) return hipSuccess;
     if (prec == kP64F) return launch_batched_step_fast64(descs, tiles, ntiles, lim, eos, nc, st);
     if (nc == 7) return launch_batched_step_react(descs, tiles, ntiles, prec, lim, st);
-    if (prec != kP64) return launch_batched_step_fast(descs, tiles, ntiles, prec, lim, eos, st);
+    if (prec == kP32) return launch_batched_step_fp32(descs, tiles, ntiles, lim, eos, st);
+    if (prec == kPMix) return launch_batched_step_fast(descs, tiles, ntiles, lim, eos, st);
     launch_batched_variants<double, double, false, 6>(descs, tiles, ntiles, lim, eos, st);
     return hipGetLastError();
 }
