@@ -1016,10 +1016,11 @@ __device__ __forceinline__ void run_tile(const Desc &d, int bx, int by, int src_
     }
     if constexpr (DIAG) {
         if (d.diag && out_col) {   // this segment's column sums (segments in row order)
-            double *part = d.diag + (long long)by * 3 * d.nx;
+            const long long n = d.nx;
+            double *part = d.diag + by * 3 * n;
             part[col] = dsum_p;
-            part[d.nx + col] = dsum_r;
-            part[2 * d.nx + col] = dsum_m;
+            part[n + col] = dsum_r;
+            part[2 * n + col] = dsum_m;
         }
         if (d.dint) {
             double isum[NC];

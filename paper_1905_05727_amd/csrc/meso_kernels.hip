@@ -347,20 +347,21 @@ __global__ void diag_row_kernel(const Control *ctl, const double *part, int nseg
                                 int ny, double *row) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nx) return;
+    const long long n = nx;   // 3 * nx may exceed the int range
     if (ctl->skip) {
-        row[i] = row[nx + i] = row[2 * nx + i] = __longlong_as_double(0x7FF8000000000000LL);
+        row[i] = row[n + i] = row[2 * n + i] = __longlong_as_double(0x7FF8000000000000LL);
         return;
     }
     double sp = 0.0, sr = 0.0, sm = 0.0;
     for (int g = 0; g < nsegs; ++g) {
-        const double *b = part + (long long)g * 3 * nx;
+        const double *b = part + g * 3 * n;
         sp = sp + b[i];
-        sr = sr + b[nx + i];
-        sm = sm + b[2 * nx + i];
+        sr = sr + b[n + i];
+        sm = sm + b[2 * n + i];
     }
     row[i] = sp / (double)ny;
-    row[nx + i] = sr / (double)ny;
-    row[2 * nx + i] = sm / sr;
+    row[n + i] = sr / (double)ny;
+    row[2 * n + i] = sm / sr;
 }
 
 // One row of a fused-integrals record: block c adds plane c's workgroup sums
