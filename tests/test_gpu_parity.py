@@ -191,6 +191,41 @@ def test_fixed_segment_height_beyond_grid(monkeypatch):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("prec", ["fp64_fast", "fp32_fp64acc"])
+def test_planes_beyond_4gib(prec):
+    """24000 x 24000 cells: each FP64 plane holds 4.6 GB, so byte offsets
+    pass 32 bits, and the two state copies take 55 GB of HBM.  The
+    two-material shock tube replicated over every row, 20 steps: every row
+    equals, bit for bit, the same tube run on a 24000 x 1 grid (y-uniform
+    data between transmissive walls: both y faces of a cell carry the same
+    flux, so the y sweep changes nothing, and the CFL maximum is the tube's),
+    and so do the time and the step count."""
+    n, steps = 24000, 20
+    tube = S.shock_tube_1d(nx=n, ny=1)
+    say(f"case: {n}x1 tube, {prec}, {steps} steps")
+    with meso.Solver.from_scenario(tube, precision=prec) as s:
+        s.run_steps(steps)
+        ref = {k: s.read_field(k)[0] for k in ("rho", "u", "p")}
+        t1 = s.time()
+    big = S.Scenario("tube_rows", n, n, tube.dx, tube.dy,
+                     np.ascontiguousarray(np.broadcast_to(tube.prim, (6, n, n))),
+                     cfl=tube.cfl, limiter=tube.limiter)
+    say(f"case: {n}x{n} replicated tube, {prec}, {steps} steps")
+    with meso.Solver.from_scenario(big, precision=prec) as s:
+        del big
+        s.run_steps(steps)
+        s.sync()
+        say("stepped; reading fields")
+        assert s.time() == t1
+        for k in ("rho", "u", "p"):
+            f = s.read_field(k)
+            same = bool(np.array_equal(f, np.broadcast_to(ref[k], f.shape)))
+            say(f"{k}: every row equals the tube: {same}")
+            assert same, k
+            del f
+    torch.cuda.empty_cache()
+
+
 def test_fp64_tall_grid_within_launch_limits():
     """A 2 x 4,500,000 column (a shock tube along y): at the height the launch
     model prefers, one strip would need more than 65535 segments, the largest
