@@ -159,7 +159,7 @@ def time_recording(sc, prec, steps, warmup):
         s.run_steps(warmup)
         s.sync()
         avg = torch.empty((steps, 3, sc.nx), dtype=torch.float64, device="cuda")
-        itg = torch.empty((steps, s.nplanes), dtype=torch.float64, device="cuda")
+        itg = torch.empty((steps, s.nplanes + 1), dtype=torch.float64, device="cuda")
         pdf = torch.empty((steps, nbins), dtype=torch.float64, device="cuda")
         for key in ("plain", "recording", "recording_all"):
             if key != "plain":

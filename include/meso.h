@@ -281,15 +281,16 @@ int32_t mf_recorded_rows(mf_solver *s, int64_t *rows);
 /* Fused domain integrals, for the remaining reactant mass M_2,r(t) of Eq.
  * (10) and the global rate of Eq. (11) at every step: while recording, each
  * step also sums every conserved plane of the state it stores, in its store
- * epilogue, and writes one row of nc doubles (the values of mf_integrals:
- * z1 rho1, z2 rho2, rho u, rho v, rho E, z1 and, reactive, M_2,r; nc = 6 or
- * 7) to dev_rows: row r is the state after the r-th step enqueued since this
- * call, NaN for a step the device skipped.  Each workgroup sums its cells
+ * epilogue, and writes one row of nc + 1 doubles to dev_rows -- the values of
+ * mf_integrals (z1 rho1, z2 rho2, rho u, rho v, rho E, z1 and, reactive,
+ * M_2,r; nc = 6 or 7), then the time of that state, so that the rate of Eq.
+ * (11) is the difference of consecutive rows: row r is the state after the
+ * r-th step enqueued since this call, all NaN for a step the device skipped.  Each workgroup sums its cells
  * (a column's rows in order, then a fixed tree over its columns) and the
  * workgroup sums are added in launch order, so a value may differ from
  * mf_integrals of the same state by up to 2 N u of the sum of magnitudes
  * (N cells, u = 2^-53) and depends on nothing but the grid and the launch
- * geometry.  dev_rows: device memory of at least nc*max_rows doubles, owned
+ * geometry.  dev_rows: device memory of at least (nc+1)*max_rows doubles, owned
  * by the caller and kept alive while recording; NULL stops.  Fused solvers
  * only; the first call allocates nc doubles per workgroup of the step launch
  * (freed by mf_destroy).  MF_E_INVALID_ARG (unfused solver, max_rows < 1,

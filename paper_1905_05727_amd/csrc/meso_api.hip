@@ -408,7 +408,7 @@ int32_t enqueue_step(mf_solver *s, double dt_fixed, double t_end) {
         ++s->rec_avg.done;
     }
     if (e == hipSuccess && ri) {
-        e = meso::launch_int_row(s->d, s->rec_int.rows + s->rec_int.done * (int64_t)s->d.nc,
+        e = meso::launch_int_row(s->d, s->rec_int.rows + s->rec_int.done * (int64_t)(s->d.nc + 1),
                                  s->stream);
         ++s->rec_int.done;
     }

@@ -139,7 +139,8 @@ hipError_t launch_histogram(const Desc &d, int prec, int src, int field, const d
 // skipped.
 hipError_t launch_diag_row(const Desc &d, double *row, hipStream_t st);
 // One row of a fused-integrals record: the nc integrals (cell area times the
-// workgroup sums at d.dint, added in workgroup order); NaN if skipped.
+// workgroup sums at d.dint, added in workgroup order) and the time of the
+// state; NaN if skipped.
 hipError_t launch_int_row(const Desc &d, double *row, hipStream_t st);
 // A fused-histogram row: zeroed before the recording step (hist_clear), then
 // divided by m_ref * dn, or NaN if the step was skipped (hist_finish).

@@ -366,7 +366,8 @@ __global__ void diag_row_kernel(const Control *ctl, const double *part, int nseg
 
 // One row of a fused-integrals record: block c adds plane c's workgroup sums
 // (thread i takes workgroups i, i + 256, ... in order, then a fixed halving
-// tree) and multiplies by the cell area; a skipped step gives NaN.
+// tree) and multiplies by the cell area; block 0 also writes the time of the
+// state after the step at row[nc].  A skipped step gives NaN throughout.
 __global__ __launch_bounds__(256) void int_row_kernel(const Control *ctl, const double *part,
                                                       int ntiles, int nc, double area,
                                                       double *row) {
@@ -374,8 +375,10 @@ __global__ __launch_bounds__(256) void int_row_kernel(const Control *ctl, const 
     const int c = blockIdx.x, t = threadIdx.x;
     if (ctl->skip) {
         if (t == 0) row[c] = __longlong_as_double(0x7FF8000000000000LL);
+        if (c == 0 && t == 0) row[nc] = __longlong_as_double(0x7FF8000000000000LL);
         return;
     }
+    if (c == 0 && t == 0) row[nc] = ctl->t;
     double s = 0.0;
     for (int g = t; g < ntiles; g += 256) s = s + part[(long long)g * nc + c];
     red[t] = s;

@@ -334,8 +334,9 @@ class Solver:
         return n.value
 
     def record_integrals(self, rows_ptr: int, max_rows: int) -> None:
-        """Record fused domain integrals (rows of `nplanes` doubles, as
-        `integrals()`) into device memory at `rows_ptr`; 0 stops."""
+        """Record fused domain integrals (rows of `nplanes` + 1 doubles: the
+        values of `integrals()`, then the time of the state) into device
+        memory at `rows_ptr`; 0 stops."""
         _chk("mf_record_integrals", self._lib.mf_record_integrals(
             self._h, C.c_void_p(rows_ptr or None), int(max_rows)))
 

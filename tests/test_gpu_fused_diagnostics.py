@@ -141,7 +141,7 @@ def test_recorded_integrals_and_pdf_match_separate_passes(prec):
     with meso.Solver.from_scenario(sc, precision=prec) as s:
         m_ref = float(s.integrals()[1])
     avg = dev_rows(nsteps + 2, 3, sc.nx)
-    itg = dev_rows(nsteps + 2, 6)
+    itg = dev_rows(nsteps + 2, 7)
     pdf = dev_rows(nsteps + 2, nbins)
     with meso.Solver.from_scenario(sc, precision=prec) as s:
         s.record_averages(avg.data_ptr(), nsteps)
@@ -163,7 +163,8 @@ def test_recorded_integrals_and_pdf_match_separate_passes(prec):
             if r < nsteps:
                 U = s.read_conserved()
                 check_averages(A[r], np.stack(s.y_averages()), U, f"{prec} averages row {r}")
-                check_integrals(I[r], s.integrals(), U, area, f"{prec} integrals row {r}")
+                check_integrals(I[r, :6], s.integrals(), U, area, f"{prec} integrals row {r}")
+                assert I[r, 6] == s.time()[0], "time of the state"
                 o.U[...] = U
                 check_pdf(F[r], s.log_histogram("p", lo, dn, nbins, m_ref),
                           o.primitive()["p"], U[1] * area / (m_ref * dn), edges,
@@ -175,7 +176,7 @@ def test_recorded_integrals_and_pdf_match_separate_passes(prec):
         Un = s.read_conserved()
     o = oracle_of(sc)
     o.U[...] = Un
-    check_integrals(I[nsteps - 1], o.integrals(), Un, area, f"{prec} last integrals vs oracle")
+    check_integrals(I[nsteps - 1, :6], o.integrals(), Un, area, f"{prec} last integrals vs oracle")
     check_pdf(F[nsteps - 1], o.log_histogram(9, lo, dn, nbins, m_ref), o.primitive()["p"],
               Un[1] * area / (m_ref * dn), edges, f"{prec} last p PDF vs oracle")
 
@@ -188,7 +189,7 @@ def test_recorded_integrals_alone(prec):
     for nx, ny in ((40, 9), (33, 49)):
         sc = bubble(nx, ny)
         say(f"case: recorded integrals alone {nx}x{ny}, {prec}")
-        itg = dev_rows(8, 6)
+        itg = dev_rows(8, 7)
         with meso.Solver.from_scenario(sc, precision=prec) as s:
             s.record_integrals(itg.data_ptr(), 8)
             s.run_steps(8)
@@ -198,8 +199,9 @@ def test_recorded_integrals_alone(prec):
         with meso.Solver.from_scenario(sc, precision=prec) as s:
             for r in range(8):
                 s.run_steps(1)
-                check_integrals(I[r], s.integrals(), s.read_conserved(), sc.dx * sc.dy,
+                check_integrals(I[r, :6], s.integrals(), s.read_conserved(), sc.dx * sc.dy,
                                 f"{nx}x{ny} row {r}")
+                assert I[r, 6] == s.time()[0]
 
 
 @pytest.mark.parametrize("prec", ["fp64_fast", "fp32_fp64acc"])
@@ -214,7 +216,7 @@ def test_recorded_pdf_full_width_and_skipped_steps(prec):
     n = sc.nx * sc.ny
     area = sc.dx * sc.dy
     say(f"case: recorded integrals + density PDF 8192x256, {prec}, then run-to-time")
-    itg = dev_rows(230, 6)
+    itg = dev_rows(230, 7)
     pdf = dev_rows(230, nbins)
     with meso.Solver.from_scenario(sc, precision=prec) as s:
         m_ref = float(s.integrals()[1])
@@ -226,7 +228,8 @@ def test_recorded_pdf_full_width_and_skipped_steps(prec):
         I, F = itg.cpu().numpy(), pdf.cpu().numpy()
         o = oracle_of(sc)
         o.U[...] = U
-        check_integrals(I[199], o.integrals(), U, area, "8192x256 row 199 integrals vs oracle")
+        check_integrals(I[199, :6], o.integrals(), U, area, "8192x256 row 199 integrals vs oracle")
+        assert I[199, 6] == t200
         fo = o.log_histogram(6, lo, dn, nbins, m_ref)
         assert np.count_nonzero(fo) > 5
         check_pdf(F[199], fo, U[0] + U[1], U[1] * area / (m_ref * dn),
@@ -260,7 +263,7 @@ def test_recorded_reactant_mass_and_qdot_pdf(prec):
     nbins, lo, dn = 400, 2.0, 0.02
     area = sc.dx * sc.dy
     say(f"case: recorded reactant mass + q-dot PDF 240x120, {prec}")
-    itg = dev_rows(20, 7)
+    itg = dev_rows(20, 8)
     pdf = dev_rows(20, nbins)
     with meso.Solver.from_scenario(sc, precision=prec) as s:
         m_tot = float(s.integrals()[1])
@@ -279,7 +282,8 @@ def test_recorded_reactant_mass_and_qdot_pdf(prec):
             s.run_steps(1)
             U = s.read_conserved()
             qd = s.read_field("qdot")
-            check_integrals(I[r], s.integrals(), U, area, f"{prec} integrals row {r}")
+            check_integrals(I[r, :7], s.integrals(), U, area, f"{prec} integrals row {r}")
+            assert I[r, 7] == s.time()[0], "time of the state"
             check_pdf(F[r], s.log_histogram("qdot", lo, dn, nbins, m_tot), qd,
                       U[1] * area / (m_tot * dn), edges, f"{prec} q-dot PDF row {r}",
                       rel=1e-12)
@@ -287,7 +291,12 @@ def test_recorded_reactant_mass_and_qdot_pdf(prec):
     assert F[19].sum() > 0.0 and np.all(I[:, 6] > 0.0)
     o = oracle_of(sc)
     o.U[...] = U
-    check_integrals(I[19], o.integrals(), U, area, f"{prec} last integrals vs oracle")
+    check_integrals(I[19, :7], o.integrals(), U, area, f"{prec} last integrals vs oracle")
+    # the global rate of Eq. (11) from consecutive rows: finite, and the
+    # reactant mass it follows is the oracle's integral of z2 rho2 lambda
+    rate = -np.diff(I[:, 6]) / np.diff(I[:, 7]) / m_tot
+    say(f"{prec} global reaction rate over the 20 steps: {rate.min():.3e} .. {rate.max():.3e} 1/s")
+    assert np.all(np.isfinite(rate)) and np.all(np.diff(I[:, 7]) > 0)
     check_pdf(F[19], o.log_histogram(14, lo, dn, nbins, m_tot), qd, U[1] * area / (m_tot * dn),
               edges, f"{prec} last q-dot PDF vs oracle", rel=1e-12)
 
