@@ -70,7 +70,8 @@ extern "C" {
 #define MF_FP64_FAST     3  /* FP64 state and arithmetic with fused multiply-adds;
                                divisions and square roots from the hardware
                                reciprocal / reciprocal-square-root seeds refined
-                               by Newton steps (a few ulp each): within 1e-12
+                               by a second-order series in their residual
+                               (about one ulp each): within 1e-12
                                relative L1 of the FP64 contract per field after
                                the fixed step counts, not bit for bit          */
 

@@ -1,6 +1,6 @@
 // meso_kernels_fast64.hip -- state-update kernels of the fast FP64 mode: FP64
 // state and arithmetic throughout, divisions and square roots from the
-// hardware seeds refined by Newton steps, built with floating-point
+// hardware seeds refined by a second-order series, built with floating-point
 // contraction (fused multiply-adds).  Inert and reactive liquids; the
 // reactive fused kernel is held to two waves per SIMD like the FP64 one.
 

@@ -1,7 +1,7 @@
 """Fast FP64 mode (MF_FP64_FAST) through the C ABI against the FP64 oracle.
 
 The mode keeps FP64 storage and arithmetic but takes divisions and square
-roots from the hardware seeds refined by Newton steps and fuses
+roots from the hardware seeds refined by a second-order series and fuses
 multiply-adds, so it is not bit-compatible with the oracle's correctly rounded
 operation sequence.  Its gate is the one stated for the FP64 path: relative L1
 <= 1e-12 per field after the fixed step count.  Momentum planes whose L1 norm
